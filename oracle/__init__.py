@@ -1,0 +1,249 @@
+"""CPU oracle for generalized canonical purification (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: the slow, obviously-correct FP64 reference the GPU
+library is checked against.  Only the tests, the smoke check and the
+benchmark's CPU-baseline leg may import it.  It shares no code with the GPU
+library (``paper_1512_07236_amd``) and never imports it.
+
+Parts:
+  * ``purify``            -- the recursion of eq. (hpcp3) step by step, plain C
+                             loops in FP64 (``gcp_oracle.c``), from the
+                             canonical initial guess of eqs. (dmguess)+(pmcpguess).
+  * ``jacobi_eigh`` / ``projector`` -- the definition of the result: the
+                             projector onto the N lowest eigenvectors of H
+                             (cyclic Jacobi, plain C).
+  * ``projector_from_spectrum`` -- the same definition when H = Q diag(lam) Q^T
+                             is known by construction (one library matmul).
+  * ``scalar_map``        -- the recursion acting on eigenvalues: because every
+                             iterate is a polynomial in H, eq. (hpcp3) maps each
+                             eigenvalue of D0 by x -> x + 2(x^2(1-x) - c x(1-x))
+                             with c formed from power sums of the eigenvalues.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gcp_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, NOT_CONVERGED, BREAKDOWN, INVALID = 0, 1, 2, -1
+HIST_COLS = 9
+HIST_FIELDS = ("n", "t1", "t2", "t3", "c", "omega", "gamma", "lagrangian", "step")
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (-O2, OpenMP) into oracle/liboracle.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER(ctypes.c_double)
+        i64, dbl, cint = ctypes.c_int64, ctypes.c_double, ctypes.c_int
+        L.oracle_matmul.argtypes = [i64, P, P, P]
+        L.oracle_matmul_rows.argtypes = [i64, i64, i64, P, P, P]
+        L.oracle_gershgorin.argtypes = [i64, P, P, P]
+        L.oracle_initial_guess.argtypes = [i64, i64, P, dbl, dbl, P, P, P]
+        L.oracle_initial_guess.restype = cint
+        L.oracle_purify_from.argtypes = [i64, i64, P, dbl, dbl, cint, P, ctypes.POINTER(cint)]
+        L.oracle_purify_from.restype = cint
+        L.oracle_purify.argtypes = [i64, i64, P, dbl, dbl, dbl, dbl, cint, P, P,
+                                    ctypes.POINTER(cint), P]
+        L.oracle_purify.restype = cint
+        L.oracle_jacobi_eigh.argtypes = [i64, P, P, P, dbl, cint]
+        L.oracle_jacobi_eigh.restype = cint
+        L.oracle_projector.argtypes = [i64, i64, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def matmul(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    A, B = _f64(A), _f64(B)
+    M = A.shape[0]
+    C = np.empty((M, M))
+    lib().oracle_matmul(M, _p(A), _p(B), _p(C))
+    return C
+
+
+def matmul_rows(A: np.ndarray, B: np.ndarray, r0: int, r1: int) -> np.ndarray:
+    A, B = _f64(A), _f64(B)
+    M = A.shape[0]
+    C = np.empty((r1 - r0, M))
+    lib().oracle_matmul_rows(M, r0, r1, _p(A), _p(B), _p(C))
+    return C
+
+
+def gershgorin(H: np.ndarray):
+    H = _f64(H)
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    lib().oracle_gershgorin(H.shape[0], _p(H), ctypes.byref(lo), ctypes.byref(hi))
+    return lo.value, hi.value
+
+
+def initial_guess(H: np.ndarray, N: int, emin: float, emax: float):
+    """Returns (D0, mu, beta); raises ValueError on invalid input."""
+    H = _f64(H)
+    M = H.shape[0]
+    D0 = np.empty((M, M))
+    mu, beta = ctypes.c_double(), ctypes.c_double()
+    st = lib().oracle_initial_guess(M, N, _p(H), emin, emax, _p(D0), ctypes.byref(mu),
+                                    ctypes.byref(beta))
+    if st != OK:
+        raise ValueError("invalid purification input (N out of range or bounds do not bracket mu)")
+    return D0, mu.value, beta.value
+
+
+@dataclass
+class Result:
+    D: np.ndarray
+    status: int
+    iters: int
+    history: np.ndarray      # (iters+1, HIST_COLS)
+    mu: float = float("nan")
+    beta: float = float("nan")
+    emin: float = float("nan")
+    emax: float = float("nan")
+
+    def col(self, name: str) -> np.ndarray:
+        return self.history[:, HIST_FIELDS.index(name)]
+
+
+def purify(H: np.ndarray, N: int, emin: float = float("nan"), emax: float = float("nan"),
+           tol_ddbar: float = 1e-6, tol_idem: float = 0.0, max_iter: int = 100) -> Result:
+    """Initial guess + HPCP recursion in FP64 (plain C).  NaN bounds -> Gershgorin."""
+    H = _f64(H)
+    M = H.shape[0]
+    D = np.empty((M, M))
+    hist = np.full((max_iter + 1, HIST_COLS), np.nan)
+    iters = ctypes.c_int()
+    scal = np.empty(4)
+    st = lib().oracle_purify(M, N, _p(H), emin, emax, tol_ddbar, tol_idem, max_iter, _p(D),
+                             _p(hist), ctypes.byref(iters), _p(scal))
+    if st == INVALID:
+        raise ValueError("invalid purification input")
+    n = iters.value
+    return Result(D, st, n, hist[: n + 1].copy(), *scal)
+
+
+def purify_from(D0: np.ndarray, N: int, tol_ddbar: float = 1e-6, tol_idem: float = 0.0,
+                max_iter: int = 100) -> Result:
+    """HPCP recursion from a given symmetric D0 (copied)."""
+    D = _f64(D0).copy()
+    M = D.shape[0]
+    hist = np.full((max_iter + 1, HIST_COLS), np.nan)
+    iters = ctypes.c_int()
+    st = lib().oracle_purify_from(M, N, _p(D), tol_ddbar, tol_idem, max_iter, _p(hist),
+                                  ctypes.byref(iters))
+    n = iters.value
+    return Result(D, st, n, hist[: n + 1].copy())
+
+
+def jacobi_eigh(A: np.ndarray, tol: float = 1e-15, max_sweeps: int = 60):
+    """Cyclic Jacobi: returns (w ascending, V with eigenvectors as columns, sweeps)."""
+    A = _f64(A)
+    M = A.shape[0]
+    w = np.empty(M)
+    V = np.empty((M, M))
+    sweeps = lib().oracle_jacobi_eigh(M, _p(A), _p(w), _p(V), tol, max_sweeps)
+    if sweeps < 0:
+        raise MemoryError("jacobi_eigh: allocation failed")
+    return w, V, sweeps
+
+
+def projector(V: np.ndarray, N: int) -> np.ndarray:
+    """Sum of v_i v_i^T over the first N columns of V (eigenvalues ascending)."""
+    V = _f64(V)
+    M = V.shape[0]
+    P = np.empty((M, M))
+    lib().oracle_projector(M, N, _p(V), _p(P))
+    return P
+
+
+def ground_state_jacobi(H: np.ndarray, N: int):
+    """Definition of the result: projector onto the N lowest eigenvectors of H.
+    Returns (P, eigenvalues ascending)."""
+    w, V, _ = jacobi_eigh(H)
+    return projector(V, N), w
+
+
+def projector_from_spectrum(Q: np.ndarray, lam: np.ndarray, N: int) -> np.ndarray:
+    """Definition of the result for H = Q diag(lam) Q^T: Q_occ Q_occ^T with occ
+    the indices of the N smallest lam (library matmul)."""
+    occ = np.argsort(lam, kind="stable")[:N]
+    Qo = np.ascontiguousarray(Q[:, occ])
+    return Qo @ Qo.T
+
+
+def scalar_map(eps: np.ndarray, N: int, emin: float, emax: float, mu: Optional[float] = None,
+               tol_ddbar: float = 1e-6, tol_idem: float = 0.0, max_iter: int = 100):
+    """The recursion on eigenvalues (H with known spectrum eps).
+
+    Every iterate is a polynomial in H, so D_n has the eigenvectors of H and
+    eigenvalues obtained from x0 = theta + beta (mu - eps) by repeatedly applying
+    eq. (hpcp3) to numbers: x <- x + 2 (x^2 (1-x) - c x (1-x)),
+    c = sum x^2(1-x) / sum x(1-x).  Returns dict(status, iters, c, t1, t2, t3,
+    omega, x) with per-iterate arrays; the same termination rule as ``purify``.
+    """
+    eps = np.asarray(eps, dtype=np.float64)
+    M = eps.size
+    theta = N / M
+    if mu is None:
+        mu = float(np.sum(eps)) / M
+    beta = 0.0
+    if 0 < N < M:
+        beta = min(theta / (emax - mu), (1 - theta) / (mu - emin))
+    x = theta + beta * (mu - eps)
+    out = {k: [] for k in ("t1", "t2", "t3", "c", "omega")}
+    status = NOT_CONVERGED
+    n = 0
+    while True:
+        t1, t2 = x.sum(), (x * x).sum()
+        omega = ((x * x - x) ** 2).sum()
+        out["t1"].append(t1); out["t2"].append(t2); out["omega"].append(omega)
+        if abs(t1 - t2) <= tol_ddbar or np.sqrt(omega) <= tol_idem:
+            status = OK
+            break
+        if n >= max_iter:
+            break
+        if t1 - t2 <= 0:
+            status = BREAKDOWN
+            break
+        t3 = (x ** 3).sum()
+        c = (t2 - t3) / (t1 - t2)
+        out["t3"].append(t3); out["c"].append(c)
+        if not (0.0 <= c <= 1.0):
+            status = BREAKDOWN
+            break
+        x = x + 2.0 * (x * x * (1 - x) - c * x * (1 - x))
+        n += 1
+    res = {k: np.array(v) for k, v in out.items()}
+    res.update(status=status, iters=n, x=x, beta=beta, mu=mu)
+    return res

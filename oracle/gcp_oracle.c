@@ -1,0 +1,350 @@
+/*
+ * gcp_oracle.c -- plain FP64 CPU oracle for generalized canonical
+ * purification (hole-particle canonical purification, HPCP).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg may load it; the GPU
+ * library never links, includes or calls it, and it shares no code with it.
+ *
+ * Everything is IEEE double, row-major, with plain loops (OpenMP over rows
+ * where a loop is embarrassingly parallel).  No BLAS, no blocking, no fusion.
+ *
+ * Paper: Truflandier, Dianzinga, Bowler, "Generalized canonical purification
+ * for density matrix minimization" (arXiv:1512.07236).  Citations below name
+ * the paper's equations:
+ *   eq. (dmguess)     D0 = beta1*I + beta2*(mu*I - H)
+ *   eq. (pmcpguess)   beta1 = theta, beta2 = min(theta/(Hmax-mu), thetabar/(mu-Hmin)),
+ *                     mu = Tr(H)/M, bounds from Gershgorin discs
+ *   eq. (hpcp3)       D_{n+1} = D_n + 2( D_n^2 Dbar_n - [Tr(D_n^2 Dbar_n)/Tr(D_n Dbar_n)] D_n Dbar_n )
+ *                     with the hole matrix Dbar = I - D (eq. closure)
+ *   termination       on Tr(D_n Dbar_n) (paper: <= 1e-6), text after eq. (hpcp3)
+ *   eq. (mcw1b)       McWeeny functional Omega = Tr((D^2 - D)^2) = ||D^2 - D||_F^2
+ *   eq. (mcw4b)       Lagrangian L = Omega - gamma (Tr(3D^2 - 2D^3) - N)
+ *   eq. (mcwgama)     gamma = 1/3 - 2/3 c   (d = 0)
+ *
+ * Where the paper is silent this file takes these readings:
+ *   - symmetry of iterates: after each update D <- (D + D^T)/2 (diagonal, and
+ *     therefore the trace, unchanged);
+ *   - termination is tested before the division that forms c, on the size of
+ *     Tr(D Dbar): |Tr(D Dbar)| <= tol_ddbar (eigenvalues may overshoot [0,1]
+ *     slightly near convergence, which makes the trace a signed sum), or on
+ *     ||D^2 - D||_F <= tol_idem;
+ *   - c outside [0,1], or Tr(D Dbar) < -tol_ddbar, before the tolerance is met
+ *     is a breakdown (the paper calls these runaway solutions); nothing is
+ *     clamped;
+ *   - the eigensolver used for the definition D = sum of the lowest-N
+ *     eigenprojectors is cyclic Jacobi (Golub & Van Loan, symmetric Schur
+ *     rotations), the textbook method, written out here.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_NOT_CONVERGED 1
+#define ORACLE_BREAKDOWN 2
+#define ORACLE_INVALID (-1)
+
+/* Number of doubles per history row written by oracle_purify. */
+#define ORACLE_HIST_COLS 9
+
+/* ------------------------------------------------------------------ */
+/* Dense building blocks                                                */
+/* ------------------------------------------------------------------ */
+
+/* C = A * B for M x M row-major matrices (i-k-j loop order). */
+void oracle_matmul(int64_t M, const double *A, const double *B, double *C)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < M; ++i) {
+        double *c = C + i * M;
+        for (int64_t j = 0; j < M; ++j) c[j] = 0.0;
+        for (int64_t k = 0; k < M; ++k) {
+            const double a = A[i * M + k];
+            const double *b = B + k * M;
+            for (int64_t j = 0; j < M; ++j) c[j] += a * b[j];
+        }
+    }
+}
+
+/* Rows [r0, r1) of C = A * B (same loop as oracle_matmul; used to time a
+ * bounded sample of the full product). C is (r1-r0) x M. */
+void oracle_matmul_rows(int64_t M, int64_t r0, int64_t r1, const double *A,
+                        const double *B, double *C)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = r0; i < r1; ++i) {
+        double *c = C + (i - r0) * M;
+        for (int64_t j = 0; j < M; ++j) c[j] = 0.0;
+        for (int64_t k = 0; k < M; ++k) {
+            const double a = A[i * M + k];
+            const double *b = B + k * M;
+            for (int64_t j = 0; j < M; ++j) c[j] += a * b[j];
+        }
+    }
+}
+
+static double trace(int64_t M, const double *A)
+{
+    double t = 0.0;
+    for (int64_t i = 0; i < M; ++i) t += A[i * M + i];
+    return t;
+}
+
+/* ------------------------------------------------------------------ */
+/* Spectral bounds and the initial guess                                */
+/* ------------------------------------------------------------------ */
+
+/* Gershgorin discs: every eigenvalue lies in some [H_ii - r_i, H_ii + r_i]
+ * with r_i = sum_{j != i} |H_ij|; the union's ends bound the spectrum. */
+void oracle_gershgorin(int64_t M, const double *H, double *emin, double *emax)
+{
+    double lo = INFINITY, hi = -INFINITY;
+    for (int64_t i = 0; i < M; ++i) {
+        double r = 0.0;
+        for (int64_t j = 0; j < M; ++j)
+            if (j != i) r += fabs(H[i * M + j]);
+        const double d = H[i * M + i];
+        if (d - r < lo) lo = d - r;
+        if (d + r > hi) hi = d + r;
+    }
+    *emin = lo;
+    *emax = hi;
+}
+
+/* Canonical (Palser-Manolopoulos) initial guess, eqs. (dmguess)+(pmcpguess):
+ *   theta = N/M, mu = Tr(H)/M,
+ *   beta_tilde = theta/(emax - mu), beta_bar = (1-theta)/(mu - emin),
+ *   beta = min(beta_tilde, beta_bar),  D0 = theta*I + beta*(mu*I - H).
+ * Returns ORACLE_INVALID when the bounds do not bracket mu (0 < N < M).
+ * For N = 0 or N = M, beta = 0 and D0 is 0 or I. */
+int oracle_initial_guess(int64_t M, int64_t N, const double *H, double emin,
+                         double emax, double *D0, double *mu_out,
+                         double *beta_out)
+{
+    if (M <= 0 || N < 0 || N > M) return ORACLE_INVALID;
+    const double theta = (double)N / (double)M;
+    const double mu = trace(M, H) / (double)M;
+    double beta = 0.0;
+    if (N > 0 && N < M) {
+        if (!(emin < mu && mu < emax)) return ORACLE_INVALID;
+        const double beta_tilde = theta / (emax - mu);
+        const double beta_bar = (1.0 - theta) / (mu - emin);
+        beta = beta_tilde < beta_bar ? beta_tilde : beta_bar;
+    }
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = 0; j < M; ++j)
+            D0[i * M + j] = (i == j ? theta + beta * mu : 0.0) - beta * H[i * M + j];
+    if (mu_out) *mu_out = mu;
+    if (beta_out) *beta_out = beta;
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* The recursion, eq. (hpcp3)                                           */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Purify D in place, starting from the given D0 (M x M, symmetric).
+ *
+ * Per iteration n:
+ *   X2 = D D,  DDbar = D - X2 (= D Dbar),  Tr(D Dbar) = Tr D - Tr X2
+ *   Omega = ||X2 - D||_F^2
+ *   stop if |Tr(D Dbar)| <= tol_ddbar or sqrt(Omega) <= tol_idem
+ *   X3 = X2 D,  D2Dbar = X2 - X3 (= D^2 Dbar)
+ *   c = Tr(D^2 Dbar) / Tr(D Dbar)
+ *   D <- D + 2 (D2Dbar - c DDbar), then D <- (D + D^T)/2
+ *
+ * hist (may be NULL) receives ORACLE_HIST_COLS doubles per evaluated
+ * iterate n = 0..iters (so iters+1 rows; room for max_iter+1 rows):
+ *   [n, Tr D, Tr D^2, Tr D^3, c, Omega, gamma, L, ||D_{n+1}-D_n||_F]
+ * (Tr D^3, c, gamma, L and the step norm are NaN on the final row).
+ * *iters = number of updates applied.  Returns ORACLE_OK,
+ * ORACLE_NOT_CONVERGED or ORACLE_BREAKDOWN.
+ */
+int oracle_purify_from(int64_t M, int64_t N, double *D, double tol_ddbar,
+                       double tol_idem, int max_iter, double *hist, int *iters)
+{
+    const int64_t MM = M * M;
+    double *X2 = (double *)malloc(sizeof(double) * MM);
+    double *X3 = (double *)malloc(sizeof(double) * MM);
+    double *T = (double *)malloc(sizeof(double) * MM);
+    if (!X2 || !X3 || !T) {
+        free(X2); free(X3); free(T);
+        return ORACLE_INVALID;
+    }
+    int status = ORACLE_NOT_CONVERGED;
+    int n = 0;
+    for (;; ++n) {
+        oracle_matmul(M, D, D, X2);
+        const double t1 = trace(M, D);
+        const double t2 = trace(M, X2);
+        double omega = 0.0;
+        for (int64_t e = 0; e < MM; ++e) {
+            const double r = X2[e] - D[e];
+            omega += r * r;
+        }
+        const double tr_ddbar = t1 - t2;
+        double *row = hist ? hist + (int64_t)n * ORACLE_HIST_COLS : NULL;
+        if (row) {
+            row[0] = n; row[1] = t1; row[2] = t2; row[5] = omega;
+            row[3] = row[4] = row[6] = row[7] = row[8] = NAN;
+        }
+        if (!isfinite(t1) || !isfinite(t2) || !isfinite(omega)) {
+            status = ORACLE_BREAKDOWN;
+            break;
+        }
+        if (fabs(tr_ddbar) <= tol_ddbar || sqrt(omega) <= tol_idem) {
+            status = ORACLE_OK;
+            break;
+        }
+        if (n >= max_iter) {
+            status = ORACLE_NOT_CONVERGED;
+            break;
+        }
+        if (tr_ddbar <= 0.0) {
+            status = ORACLE_BREAKDOWN;
+            break;
+        }
+        oracle_matmul(M, X2, D, X3);
+        const double t3 = trace(M, X3);
+        const double tr_d2dbar = t2 - t3;
+        const double c = tr_d2dbar / tr_ddbar;
+        const double gamma = 1.0 / 3.0 - 2.0 / 3.0 * c;
+        if (row) {
+            row[3] = t3; row[4] = c; row[6] = gamma;
+            row[7] = omega - gamma * (3.0 * t2 - 2.0 * t3 - (double)N);
+        }
+        if (!isfinite(c) || c < 0.0 || c > 1.0) {
+            status = ORACLE_BREAKDOWN;
+            break;
+        }
+        /* D' = D + 2 (D^2 Dbar - c D Dbar) */
+        for (int64_t e = 0; e < MM; ++e) {
+            const double d2dbar = X2[e] - X3[e];
+            const double ddbar = D[e] - X2[e];
+            T[e] = D[e] + 2.0 * (d2dbar - c * ddbar);
+        }
+        double step = 0.0;
+        for (int64_t i = 0; i < M; ++i)
+            for (int64_t j = 0; j < M; ++j) {
+                const double s = 0.5 * (T[i * M + j] + T[j * M + i]);
+                const double dd = s - D[i * M + j];
+                step += dd * dd;
+                X3[i * M + j] = s;
+            }
+        if (row) row[8] = sqrt(step);
+        memcpy(D, X3, sizeof(double) * MM);
+    }
+    *iters = n;
+    free(X2); free(X3); free(T);
+    return status;
+}
+
+/* Initial guess from (H, N, bounds) followed by the recursion.  NaN bounds
+ * select the Gershgorin bounds.  mu/beta/emin/emax are reported in
+ * scal[0..3] when scal is not NULL. */
+int oracle_purify(int64_t M, int64_t N, const double *H, double emin,
+                  double emax, double tol_ddbar, double tol_idem, int max_iter,
+                  double *D, double *hist, int *iters, double *scal)
+{
+    if (isnan(emin) || isnan(emax)) oracle_gershgorin(M, H, &emin, &emax);
+    double mu = 0.0, beta = 0.0;
+    const int st = oracle_initial_guess(M, N, H, emin, emax, D, &mu, &beta);
+    if (scal) { scal[0] = mu; scal[1] = beta; scal[2] = emin; scal[3] = emax; }
+    if (st != ORACLE_OK) { *iters = 0; return st; }
+    return oracle_purify_from(M, N, D, tol_ddbar, tol_idem, max_iter, hist, iters);
+}
+
+/* ------------------------------------------------------------------ */
+/* Definition: projector onto the lowest-N eigenvectors (Jacobi)        */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Cyclic Jacobi eigensolver for a symmetric M x M matrix A (not modified).
+ * w receives the eigenvalues in ascending order and V (row-major) the
+ * matching eigenvectors as columns: A = V diag(w) V^T.
+ * Sweeps stop when the off-diagonal Frobenius norm falls below
+ * tol * ||A||_F or after max_sweeps.  Returns the number of sweeps, or -1.
+ */
+int oracle_jacobi_eigh(int64_t M, const double *A_in, double *w, double *V,
+                       double tol, int max_sweeps)
+{
+    double *A = (double *)malloc(sizeof(double) * M * M);
+    if (!A) return -1;
+    memcpy(A, A_in, sizeof(double) * M * M);
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = 0; j < M; ++j) V[i * M + j] = (i == j) ? 1.0 : 0.0;
+    double fro = 0.0;
+    for (int64_t e = 0; e < M * M; ++e) fro += A[e] * A[e];
+    fro = sqrt(fro);
+    int sweep = 0;
+    for (; sweep < max_sweeps; ++sweep) {
+        double off = 0.0;
+        for (int64_t p = 0; p < M; ++p)
+            for (int64_t q = 0; q < M; ++q)
+                if (p != q) off += A[p * M + q] * A[p * M + q];
+        if (sqrt(off) <= tol * fro) break;
+        for (int64_t p = 0; p < M - 1; ++p) {
+            for (int64_t q = p + 1; q < M; ++q) {
+                const double apq = A[p * M + q];
+                if (apq == 0.0) continue;
+                /* Symmetric Schur decomposition of the 2x2 block (p, q). */
+                const double tau = (A[q * M + q] - A[p * M + p]) / (2.0 * apq);
+                const double t = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                                              : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+                const double c = 1.0 / sqrt(1.0 + t * t);
+                const double s = t * c;
+                /* A <- J^T A J with J = [[c, s], [-s, c]] in the (p, q) plane. */
+                for (int64_t k = 0; k < M; ++k) {   /* columns p, q */
+                    const double akp = A[k * M + p], akq = A[k * M + q];
+                    A[k * M + p] = c * akp - s * akq;
+                    A[k * M + q] = s * akp + c * akq;
+                }
+                for (int64_t k = 0; k < M; ++k) {   /* rows p, q */
+                    const double apk = A[p * M + k], aqk = A[q * M + k];
+                    A[p * M + k] = c * apk - s * aqk;
+                    A[q * M + k] = s * apk + c * aqk;
+                }
+                A[p * M + q] = A[q * M + p] = 0.0;
+                for (int64_t k = 0; k < M; ++k) {   /* V <- V J */
+                    const double vkp = V[k * M + p], vkq = V[k * M + q];
+                    V[k * M + p] = c * vkp - s * vkq;
+                    V[k * M + q] = s * vkp + c * vkq;
+                }
+            }
+        }
+    }
+    /* Sort ascending (selection sort on the diagonal, swapping V columns). */
+    for (int64_t i = 0; i < M; ++i) w[i] = A[i * M + i];
+    for (int64_t i = 0; i < M; ++i) {
+        int64_t m = i;
+        for (int64_t j = i + 1; j < M; ++j)
+            if (w[j] < w[m]) m = j;
+        if (m != i) {
+            const double tw = w[i]; w[i] = w[m]; w[m] = tw;
+            for (int64_t k = 0; k < M; ++k) {
+                const double tv = V[k * M + i];
+                V[k * M + i] = V[k * M + m];
+                V[k * M + m] = tv;
+            }
+        }
+    }
+    free(A);
+    return sweep;
+}
+
+/* P = sum_{i < N} v_i v_i^T  (columns of V, eigenvalues sorted ascending):
+ * the N-representable ground-state density matrix when e_N < e_{N+1}. */
+void oracle_projector(int64_t M, int64_t N, const double *V, double *P)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = 0; j < M; ++j) {
+            double s = 0.0;
+            for (int64_t k = 0; k < N; ++k) s += V[i * M + k] * V[j * M + k];
+            P[i * M + j] = s;
+        }
+}
