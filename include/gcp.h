@@ -1,0 +1,157 @@
+/*
+ * gcp.h -- C ABI of libgcp: generalized canonical purification on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library computes the ground-state one-particle density matrix D of a
+ * real symmetric Hamiltonian H (M states, N occupied) without
+ * diagonalisation, by the hole-particle canonical purification (HPCP) of
+ * Truflandier, Dianzinga & Bowler, arXiv:1512.07236:
+ *
+ *   D_0     = theta I + beta (mu I - H)                          eqs. (dmguess),(pmcpguess)
+ *             theta = N/M, mu = Tr(H)/M,
+ *             beta  = min(theta/(emax - mu), (1-theta)/(mu - emin))
+ *   D_{n+1} = D_n + 2 (D_n^2 Dbar_n - c_n D_n Dbar_n),  Dbar = I - D      eq. (hpcp3)
+ *   c_n     = Tr(D_n^2 Dbar_n) / Tr(D_n Dbar_n)
+ *
+ * iterated until Tr(D_n Dbar_n) (the paper's criterion) or ||D_n^2 - D_n||_F
+ * falls below a tolerance.  Tr D_n = N holds at every step by construction
+ * (no a-posteriori trace correction).  Each iteration costs two symmetric
+ * matrix products (D^2 and D^2 D), the paper's "two matrix multiplications".
+ *
+ * Conventions for every entry point
+ *  - Matrices are dense, row-major, with a leading dimension (elements)
+ *    >= M.  All matrix pointers are DEVICE pointers on the GPU that was
+ *    current when the context was created, owned by the caller.
+ *  - Work is enqueued on the stream given to gcp_create (a hipStream_t passed
+ *    as void*; NULL = the default stream).  Entry points that must decide on
+ *    the host (gcp_init, gcp_purify, gcp_backward) synchronise that stream.
+ *  - Every function returns a gcp_status; nothing throws across the ABI.
+ *    gcp_last_error() gives a text description of the last failure.
+ *  - A context is not thread-safe; use one context per stream.
+ */
+#ifndef GCP_H
+#define GCP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gcp_ctx gcp_ctx;
+
+typedef enum {
+    GCP_OK = 0,
+    GCP_ERR_INVALID_ARG = -1,   /* bad size, pointer, dtype, tolerance or bounds */
+    GCP_ERR_HIP = -2,           /* a HIP runtime call failed (text in gcp_last_error) */
+    GCP_ERR_NO_MEMORY = -3,     /* device or pinned-host allocation failed */
+    GCP_ERR_NOT_CONVERGED = -4, /* max_iter updates applied without meeting a tolerance */
+    GCP_ERR_BREAKDOWN = -5,     /* c_n outside [0,1], Tr(D Dbar) < 0, or a non-finite
+                                   value before convergence (the paper's runaway case) */
+    GCP_ERR_STATE = -6,         /* call out of order (purify before init, ...) */
+    GCP_ERR_UNSUPPORTED = -7    /* option combination not available */
+} gcp_status;
+
+/* Arithmetic of the two matrix products per iteration.  Traces, the
+ * coefficient c_n, the diagonal of D, D^2 and D^3 and the termination test
+ * are FP64 in every mode; off-diagonal iterates are stored in the product's
+ * operand encoding.
+ *   FP64     FP64 MFMA, FP64 storage.
+ *   FP32     FP32 MFMA, FP32 storage.
+ *   BF16     one bfloat16 operand, FP32 accumulate.
+ *   FP16     one float16 operand (scaled by 2^10), FP32 accumulate.
+ *   BF16X3   bfloat16 hi+lo split, 3 products (hi*hi, hi*lo, lo*hi).
+ *   FP16X3   float16 hi+lo split of 2^10 x, 3 products (about 22 bits).
+ *   BF16X6   bfloat16 hi+mid+lo split, 6 products (about 24 bits).        */
+typedef enum {
+    GCP_FP64 = 0,
+    GCP_FP32 = 1,
+    GCP_BF16 = 2,
+    GCP_FP16 = 3,
+    GCP_BF16X3 = 4,
+    GCP_FP16X3 = 5,
+    GCP_BF16X6 = 6
+} gcp_precision;
+
+/* Element types of caller buffers. */
+typedef enum { GCP_DTYPE_F64 = 0, GCP_DTYPE_F32 = 1 } gcp_dtype;
+
+typedef struct {
+    int32_t precision;   /* gcp_precision */
+    int32_t max_iter;    /* maximum number of updates (default 100) */
+    double tol_ddbar;    /* stop when |Tr(D Dbar)| <= tol_ddbar (default 1e-6, the paper's) */
+    double tol_idem;     /* stop when ||D^2 - D||_F <= tol_idem (default 0 = off) */
+    int32_t fold_every;  /* 16-bit encodings: fold the FP32 main accumulator into a
+                            second FP32 total every fold_every*32 columns of K
+                            (0 = never; shortens the rounding chain, costs registers) */
+    int32_t profile;     /* 1: time every matrix-product launch with HIP events */
+} gcp_options;
+
+typedef struct {
+    int32_t status;      /* gcp_status of the solve */
+    int32_t iters;       /* updates applied (p) */
+    double t1;           /* Tr D of the returned matrix (FP64) */
+    double t2;           /* Tr D^2 (FP64) */
+    double c_last;       /* last coefficient c_n used */
+    double idem;         /* ||D^2 - D||_F of the returned matrix (from the last D^2) */
+    double ms_total;     /* wall time of gcp_purify on the host clock (ms) */
+    double gemm_ms;      /* summed device time of the matrix-product launches (profile=1) */
+    int32_t gemm_launches; /* number of matrix-product launches */
+    int32_t pad;
+    double gemm_flops;   /* algorithmic flops of those launches (M^3 per product,
+                            upper-triangle output; split products not counted) */
+    double mfma_flops;   /* flops issued to the matrix cores (whole 128x128 tiles of the
+                            padded size, times the number of split products) */
+} gcp_result;
+
+/* Fills *opt with the defaults listed above (precision FP64). */
+int gcp_options_default(gcp_options *opt);
+
+/* Creates a context for M x M problems on the current device and the given
+ * stream and allocates its device workspace (about 3 M^2 operand-encoding
+ * elements plus O(M^2 / 128) FP64 partial sums).  M >= 1; M is padded
+ * internally to a multiple of 128 with zero rows/columns (exact: the padding
+ * is an invariant zero block).  *ctx is set to NULL on failure. */
+int gcp_create(gcp_ctx **ctx, int64_t M, const gcp_options *opt, void *stream);
+
+/* Releases the context and its workspace (NULL is accepted). */
+void gcp_destroy(gcp_ctx *ctx);
+
+/* Builds D_0 from H (device FP64, M x M, leading dimension ldh >= M) and N,
+ * eqs. (dmguess)+(pmcpguess).  emin/emax must bound the spectrum of H; if
+ * either is NaN the Gershgorin bounds (section on the initial guess) are
+ * used.  H is read as (H + H^T)/2.  H is not retained after the call.
+ * Errors: INVALID_ARG for N outside [0, M], ldh < M, NULL H, emin >= emax, or
+ * mu = Tr(H)/M outside (emin, emax) when 0 < N < M. */
+int gcp_init(gcp_ctx *ctx, const double *H, int64_t ldh, int64_t N, double emin,
+             double emax);
+
+/* Runs the recursion of eq. (hpcp3) from the current D_0 and writes the
+ * converged density matrix to D (device, M x M, leading dimension ldd,
+ * dtype gcp_dtype).  D is valid once the context's stream is synchronised.
+ * Returns OK on convergence, NOT_CONVERGED or BREAKDOWN otherwise (D then
+ * holds the last iterate and *out is filled in every case; out may be NULL).
+ * Calling it again re-runs the solve from the D_0 of the last gcp_init. */
+int gcp_purify(gcp_ctx *ctx, void *D, int32_t dtype, int64_t ldd, gcp_result *out);
+
+/* Per-iterate history of the last gcp_purify: GCP_HIST_COLS doubles per row,
+ *   [n, Tr D, Tr D^2, Tr D^3, c_n, Omega = ||D^2-D||_F^2, gamma_n = (1-2c_n)/3,
+ *    L_n = Omega - gamma_n (3 Tr D^2 - 2 Tr D^3 - N) (eq. mcw4b), ||D_{n+1} - D_n||_F]
+ * for n = 0..iters (the last row has NaN where no update followed).
+ * rows may be NULL to query *n_rows. */
+#define GCP_HIST_COLS 9
+int gcp_get_history(const gcp_ctx *ctx, double *rows, int32_t max_rows, int32_t *n_rows);
+
+/* Scalars of the last gcp_init: mu, beta, emin, emax (bounds actually used). */
+int gcp_get_init_scalars(const gcp_ctx *ctx, double *mu, double *beta, double *emin,
+                         double *emax);
+
+/* Text of the last error on this context (or of the last failed gcp_create
+ * when ctx is NULL).  The pointer stays valid until the next call. */
+const char *gcp_last_error(const gcp_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GCP_H */

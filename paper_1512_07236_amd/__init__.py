@@ -1,0 +1,253 @@
+"""GPU generalized canonical purification on AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding over ``lib/libgcp.so`` (C ABI: ``include/gcp.h``).  This
+module only marshals arguments: every step of the purification runs in the
+library's HIP kernels.  PyTorch supplies device memory and the stream.  If the
+library is missing or cannot be loaded, importing the binding's entry points
+raises; there is no CPU fallback.
+
+Typical use::
+
+    import torch, paper_1512_07236_amd as gcp
+    H = torch.as_tensor(H_np, device="cuda")            # FP64, symmetric
+    D, info = gcp.purify(H, N, emin=-1.0, emax=1.0, precision="fp16x3")
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from enum import IntEnum
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libgcp.so")
+
+
+class Precision(IntEnum):
+    FP64 = 0
+    FP32 = 1
+    BF16 = 2
+    FP16 = 3
+    BF16X3 = 4
+    FP16X3 = 5
+    BF16X6 = 6
+
+    @classmethod
+    def parse(cls, p) -> "Precision":
+        if isinstance(p, cls):
+            return p
+        if isinstance(p, int):
+            return cls(p)
+        return cls[str(p).upper()]
+
+
+# products per matrix multiplication (split encodings issue several)
+PRODUCTS = {Precision.FP64: 1, Precision.FP32: 1, Precision.BF16: 1, Precision.FP16: 1,
+            Precision.BF16X3: 3, Precision.FP16X3: 3, Precision.BF16X6: 6}
+# MFMA data type each precision issues
+MFMA_DTYPE = {Precision.FP64: "fp64", Precision.FP32: "fp32", Precision.BF16: "bf16",
+              Precision.FP16: "fp16", Precision.BF16X3: "bf16", Precision.FP16X3: "fp16",
+              Precision.BF16X6: "bf16"}
+
+OK, ERR_INVALID_ARG, ERR_HIP, ERR_NO_MEMORY, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_STATE, \
+    ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {OK: "OK", ERR_INVALID_ARG: "INVALID_ARG", ERR_HIP: "HIP", ERR_NO_MEMORY: "NO_MEMORY",
+                ERR_NOT_CONVERGED: "NOT_CONVERGED", ERR_BREAKDOWN: "BREAKDOWN",
+                ERR_STATE: "STATE", ERR_UNSUPPORTED: "UNSUPPORTED"}
+DTYPE_F64, DTYPE_F32 = 0, 1
+HIST_COLS = 9
+HIST_FIELDS = ("n", "t1", "t2", "t3", "c", "omega", "gamma", "lagrangian", "step")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("tol_ddbar", ctypes.c_double), ("tol_idem", ctypes.c_double),
+                ("fold_every", ctypes.c_int32), ("profile", ctypes.c_int32)]
+
+
+class CResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("t1", ctypes.c_double), ("t2", ctypes.c_double), ("c_last", ctypes.c_double),
+                ("idem", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("gemm_ms", ctypes.c_double), ("gemm_launches", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("gemm_flops", ctypes.c_double),
+                ("mfma_flops", ctypes.c_double)]
+
+
+class GCPError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load libgcp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libgcp.so not found at {LIB_PATH}; build it with "
+                          "`python -m paper_1512_07236_amd._build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.gcp_options_default.argtypes = [ctypes.POINTER(Options)]
+    L.gcp_options_default.restype = ctypes.c_int
+    L.gcp_create.argtypes = [ctypes.POINTER(vp), i64, ctypes.POINTER(Options), vp]
+    L.gcp_create.restype = ctypes.c_int
+    L.gcp_destroy.argtypes = [vp]
+    L.gcp_destroy.restype = None
+    L.gcp_init.argtypes = [vp, vp, i64, i64, dbl, dbl]
+    L.gcp_init.restype = ctypes.c_int
+    L.gcp_purify.argtypes = [vp, vp, i32, i64, ctypes.POINTER(CResult)]
+    L.gcp_purify.restype = ctypes.c_int
+    L.gcp_get_history.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32)]
+    L.gcp_get_history.restype = ctypes.c_int
+    L.gcp_get_init_scalars.argtypes = [vp] + [ctypes.POINTER(ctypes.c_double)] * 4
+    L.gcp_get_init_scalars.restype = ctypes.c_int
+    L.gcp_last_error.argtypes = [vp]
+    L.gcp_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def default_options() -> Options:
+    o = Options()
+    load_library().gcp_options_default(ctypes.byref(o))
+    return o
+
+
+@dataclass
+class Result:
+    status: int
+    iters: int
+    t1: float
+    t2: float
+    c_last: float
+    idem: float
+    ms_total: float
+    gemm_ms: float
+    gemm_launches: int
+    gemm_flops: float
+    mfma_flops: float
+    history: np.ndarray
+
+    @property
+    def ok(self) -> bool:
+        return self.status == OK
+
+    def col(self, name: str) -> np.ndarray:
+        return self.history[:, HIST_FIELDS.index(name)]
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Context:
+    """A purification context for M x M problems (owns the device workspace)."""
+
+    def __init__(self, M: int, precision="fp64", max_iter: int = 100, tol_ddbar: float = 1e-6,
+                 tol_idem: float = 0.0, fold_every: int = 0, profile: bool = False, stream=None):
+        L = load_library()
+        self._L = L
+        self.M = int(M)
+        self.precision = Precision.parse(precision)
+        o = default_options()
+        o.precision = int(self.precision)
+        o.max_iter = int(max_iter)
+        o.tol_ddbar = float(tol_ddbar)
+        o.tol_idem = float(tol_idem)
+        o.fold_every = int(fold_every)
+        o.profile = 1 if profile else 0
+        self.options = o
+        self._stream = stream
+        h = ctypes.c_void_p()
+        st = L.gcp_create(ctypes.byref(h), self.M, ctypes.byref(o),
+                          ctypes.c_void_p(_stream_handle(stream)))
+        if st != OK:
+            raise GCPError(st, L.gcp_last_error(None).decode())
+        self._h = h
+        self._H = None
+
+    def _check(self, st: int, allow=(OK,)):
+        if st not in allow:
+            raise GCPError(st, self._L.gcp_last_error(self._h).decode())
+        return st
+
+    def init(self, H, N: int, emin: float = math.nan, emax: float = math.nan) -> None:
+        import torch
+        if not (isinstance(H, torch.Tensor) and H.is_cuda and H.dtype == torch.float64):
+            raise TypeError("H must be a CUDA float64 tensor")
+        if H.dim() != 2 or H.shape[0] != self.M or H.shape[1] != self.M or H.stride(1) != 1:
+            raise ValueError(f"H must be {self.M} x {self.M} with unit column stride")
+        self._check(self._L.gcp_init(self._h, ctypes.c_void_p(H.data_ptr()), H.stride(0), int(N),
+                                     float(emin), float(emax)))
+        self.N = int(N)
+
+    def purify(self, out=None, dtype=None, raise_on_failure: bool = False):
+        """Returns (D, Result).  D is a new (or the given) CUDA tensor."""
+        import torch
+        if out is None:
+            dtype = dtype or torch.float64
+            out = torch.empty((self.M, self.M), dtype=dtype, device="cuda")
+        if out.dtype not in (torch.float64, torch.float32) or out.stride(1) != 1 or \
+                tuple(out.shape) != (self.M, self.M):
+            raise ValueError("out must be an M x M float64/float32 CUDA tensor with unit column stride")
+        dt = DTYPE_F64 if out.dtype == torch.float64 else DTYPE_F32
+        r = CResult()
+        st = self._L.gcp_purify(self._h, ctypes.c_void_p(out.data_ptr()), dt, out.stride(0),
+                                ctypes.byref(r))
+        allowed = (OK,) if raise_on_failure else (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN)
+        self._check(st, allowed)
+        return out, Result(r.status, r.iters, r.t1, r.t2, r.c_last, r.idem, r.ms_total, r.gemm_ms,
+                           r.gemm_launches, r.gemm_flops, r.mfma_flops, self.history())
+
+    def history(self) -> np.ndarray:
+        n = ctypes.c_int32()
+        self._check(self._L.gcp_get_history(self._h, None, 0, ctypes.byref(n)))
+        rows = np.full((max(n.value, 0), HIST_COLS), np.nan)
+        if n.value > 0:
+            self._check(self._L.gcp_get_history(
+                self._h, rows.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n.value,
+                ctypes.byref(n)))
+        return rows
+
+    def init_scalars(self) -> dict:
+        v = [ctypes.c_double() for _ in range(4)]
+        self._check(self._L.gcp_get_init_scalars(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("mu", "beta", "emin", "emax"), (x.value for x in v)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._L.gcp_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def purify(H, N: int, emin: float = math.nan, emax: float = math.nan, precision="fp64",
+           out=None, **options):
+    """One-shot solve: returns (D, Result)."""
+    with Context(H.shape[0], precision=precision, **options) as ctx:
+        ctx.init(H, N, emin, emax)
+        return ctx.purify(out=out)

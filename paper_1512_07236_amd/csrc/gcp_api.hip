@@ -1,0 +1,473 @@
+// gcp_api.hip -- host side of libgcp: the C ABI declared in include/gcp.h.
+//
+// Owns the device workspace of one solve and drives the iteration: per
+// update two MFMA products (gcp_kernels.hip) and two fixed-order reductions;
+// the host reads five FP64 scalars after each D^2 to decide whether to stop
+// (the paper's test on Tr(D Dbar) is made before c_n is formed).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gcp.h"
+#include "gcp_kernels.h"
+
+using namespace gcp;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int plane_count(int prec) {
+  switch (prec) {
+    case GCP_BF16X3:
+    case GCP_FP16X3: return 2;
+    case GCP_BF16X6: return 3;
+    default: return 1;
+  }
+}
+int elem_size(int prec) {
+  switch (prec) {
+    case GCP_FP64: return 8;
+    case GCP_FP32: return 4;
+    default: return 2;
+  }
+}
+int products(int prec) {
+  switch (prec) {
+    case GCP_BF16X3:
+    case GCP_FP16X3: return 3;
+    case GCP_BF16X6: return 6;
+    default: return 1;
+  }
+}
+
+}  // namespace
+
+struct gcp_ctx {
+  int64_t M = 0, Mp = 0;
+  int nt = 0, ntiles = 0, nred = 0;
+  gcp_options opt{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  // operand planes: D (double-buffered) and X2
+  void *Dp[2] = {nullptr, nullptr};
+  void *X2p = nullptr;
+  int cur = 0;
+  // FP64 vectors (length Mp)
+  double *dg[2] = {nullptr, nullptr}, *rD[2] = {nullptr, nullptr};
+  double *d2[2] = {nullptr, nullptr};
+  double *s2 = nullptr, *d3 = nullptr;
+  double *part = nullptr, *tpart = nullptr, *bpart = nullptr;
+  double *hvec = nullptr;   // 3 Mp scratch for H statistics
+  unsigned *counter = nullptr;
+  Scalars *sc = nullptr;    // device
+  Scalars *sc_host = nullptr;  // pinned
+  double *hist = nullptr;   // device, (max_iter + 1) x 9
+  std::vector<double> hist_host;
+  int hist_rows = 0;
+  // init state
+  bool inited = false;
+  int64_t N = 0;
+  double mu = NAN, beta = NAN, emin = NAN, emax = NAN;
+  double t1_0 = NAN, t2_0 = NAN;
+  void *D0p = nullptr;      // copy of the D_0 planes so purify can be re-run
+  double *dg0 = nullptr, *rD0 = nullptr, *d20 = nullptr;
+  // profiling
+  std::vector<hipEvent_t> events;
+  std::string err;
+};
+
+#define HIPCHK(ctx, expr)                                                          \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);             \
+      return GCP_ERR_HIP;                                                          \
+    }                                                                              \
+  } while (0)
+
+static size_t plane_bytes(const gcp_ctx *c) {
+  return (size_t)plane_count(c->opt.precision) * (size_t)c->Mp * (size_t)c->Mp *
+         (size_t)elem_size(c->opt.precision);
+}
+
+static void free_all(gcp_ctx *c) {
+  void *ptrs[] = {c->Dp[0], c->Dp[1], c->X2p, c->dg[0], c->dg[1], c->rD[0], c->rD[1],
+                  c->d2[0], c->d2[1], c->s2, c->d3, c->part, c->tpart, c->bpart, c->hvec,
+                  c->counter, c->sc, c->hist, c->D0p, c->dg0, c->rD0, c->d20};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->sc_host) (void)hipHostFree(c->sc_host);
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  c->events.clear();
+}
+
+extern "C" int gcp_options_default(gcp_options *opt) {
+  if (!opt) return GCP_ERR_INVALID_ARG;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->precision = GCP_FP64;
+  opt->max_iter = 100;
+  opt->tol_ddbar = 1e-6;
+  opt->tol_idem = 0.0;
+  opt->fold_every = 0;
+  opt->profile = 0;
+  return GCP_OK;
+}
+
+extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void *stream) {
+  if (!out) {
+    g_create_error = "gcp_create: ctx pointer is NULL";
+    return GCP_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  gcp_options o;
+  if (opt) o = *opt; else gcp_options_default(&o);
+  if (M <= 0 || M > (int64_t)1 << 20) {
+    g_create_error = "gcp_create: M must be in [1, 2^20]";
+    return GCP_ERR_INVALID_ARG;
+  }
+  if (o.precision < GCP_FP64 || o.precision > GCP_BF16X6) {
+    g_create_error = "gcp_create: unknown precision";
+    return GCP_ERR_INVALID_ARG;
+  }
+  if (o.max_iter < 0 || o.max_iter > 100000 || !(o.tol_ddbar >= 0.0) || !(o.tol_idem >= 0.0) ||
+      o.fold_every < 0) {
+    g_create_error = "gcp_create: max_iter, tolerances and fold_every must be non-negative";
+    return GCP_ERR_INVALID_ARG;
+  }
+  gcp_ctx *c = new (std::nothrow) gcp_ctx();
+  if (!c) {
+    g_create_error = "gcp_create: out of host memory";
+    return GCP_ERR_NO_MEMORY;
+  }
+  c->M = M;
+  c->Mp = (M + 127) / 128 * 128;
+  c->nt = (int)(c->Mp / 128);
+  c->ntiles = c->nt * (c->nt + 1) / 2;
+  c->nred = (int)((c->Mp + 255) / 256);
+  c->opt = o;
+  c->stream = (hipStream_t)stream;
+  (void)hipGetDevice(&c->device);
+
+  const size_t Mp = (size_t)c->Mp;
+  const size_t vec = Mp * sizeof(double);
+  const int nslots_max = (int)(c->Mp / 64);  // the initial guess uses 64-wide column slots
+  bool ok = true;
+  auto alloc = [&](void **p, size_t bytes) {
+    if (!ok) return;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      ok = false;
+      *p = nullptr;
+    }
+  };
+  const size_t pb = plane_bytes(c);
+  alloc(&c->Dp[0], pb);
+  alloc(&c->Dp[1], pb);
+  alloc(&c->X2p, pb);
+  alloc(&c->D0p, pb);
+  for (int k = 0; k < 2; ++k) {
+    alloc((void **)&c->dg[k], vec);
+    alloc((void **)&c->rD[k], vec);
+    alloc((void **)&c->d2[k], vec);
+  }
+  alloc((void **)&c->s2, vec);
+  alloc((void **)&c->d3, vec);
+  alloc((void **)&c->dg0, vec);
+  alloc((void **)&c->rD0, vec);
+  alloc((void **)&c->d20, vec);
+  alloc((void **)&c->part, (size_t)nslots_max * vec);
+  alloc((void **)&c->tpart, (size_t)c->ntiles * sizeof(double));
+  alloc((void **)&c->bpart, (size_t)2 * c->nred * sizeof(double));
+  alloc((void **)&c->hvec, 3 * vec);
+  alloc((void **)&c->counter, sizeof(unsigned));
+  alloc((void **)&c->sc, sizeof(Scalars));
+  alloc((void **)&c->hist, (size_t)(o.max_iter + 1) * GCP_HIST_COLS * sizeof(double));
+  if (ok && hipHostMalloc((void **)&c->sc_host, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
+    ok = false;
+  if (!ok) {
+    free_all(c);
+    delete c;
+    g_create_error = "gcp_create: device allocation failed";
+    return GCP_ERR_NO_MEMORY;
+  }
+  if (hipMemsetAsync(c->counter, 0, sizeof(unsigned), c->stream) != hipSuccess ||
+      hipMemsetAsync(c->s2, 0, vec, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    free_all(c);
+    delete c;
+    g_create_error = "gcp_create: initialisation of the workspace failed";
+    return GCP_ERR_HIP;
+  }
+  *out = c;
+  return GCP_OK;
+}
+
+extern "C" void gcp_destroy(gcp_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+}
+
+extern "C" const char *gcp_last_error(const gcp_ctx *c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+static int reduce(gcp_ctx *c, const double *part, int nslots, int mode, double *out,
+                  const double *extra, const double *tpart, int iter) {
+  RedArgs a{};
+  a.part = part;
+  a.nslots = nslots;
+  a.mode = mode;
+  a.Mp = c->Mp;
+  a.out = out;
+  a.extra = extra;
+  a.bpart = c->bpart;
+  a.counter = c->counter;
+  a.tpart = tpart;
+  a.ntiles = c->ntiles;
+  a.iter = iter;
+  a.max_iter = c->opt.max_iter;
+  a.tol_ddbar = c->opt.tol_ddbar;
+  a.tol_idem = c->opt.tol_idem;
+  a.N = (double)c->N;
+  a.sc = c->sc;
+  a.hist = c->hist;
+  HIPCHK(c, launch_reduce(a, c->stream));
+  return GCP_OK;
+}
+
+extern "C" int gcp_init(gcp_ctx *c, const double *H, int64_t ldh, int64_t N, double emin,
+                        double emax) {
+  if (!c) return GCP_ERR_INVALID_ARG;
+  c->inited = false;
+  if (!H || ldh < c->M || N < 0 || N > c->M) {
+    c->err = "gcp_init: need H != NULL, ldh >= M and 0 <= N <= M";
+    return GCP_ERR_INVALID_ARG;
+  }
+  const bool given = !std::isnan(emin) && !std::isnan(emax);
+  if (given && !(emin < emax)) {
+    c->err = "gcp_init: emin must be < emax";
+    return GCP_ERR_INVALID_ARG;
+  }
+  const size_t vec = (size_t)c->Mp * sizeof(double);
+  double *lo = c->hvec, *hi = c->hvec + c->Mp, *hd = c->hvec + 2 * c->Mp;
+  HIPCHK(c, launch_hstats(H, ldh, c->M, lo, hi, hd, c->sc->hstat, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const double g_lo = c->sc_host->hstat[0], g_hi = c->sc_host->hstat[1];
+  const double trH = c->sc_host->hstat[2];
+  if (!given) {
+    emin = g_lo;
+    emax = g_hi;
+  }
+  const double M = (double)c->M;
+  const double theta = (double)N / M;
+  const double mu = trH / M;
+  double beta = 0.0;
+  if (N > 0 && N < c->M) {
+    if (!(emin < mu && mu < emax)) {
+      c->err = "gcp_init: mu = Tr(H)/M must lie strictly inside (emin, emax)";
+      return GCP_ERR_INVALID_ARG;
+    }
+    const double bt = theta / (emax - mu), bb = (1.0 - theta) / (mu - emin);
+    beta = bt < bb ? bt : bb;
+  }
+  c->N = N;
+  c->mu = mu;
+  c->beta = beta;
+  c->emin = emin;
+  c->emax = emax;
+
+  InitArgs a{};
+  a.H = H;
+  a.ldh = ldh;
+  a.M = c->M;
+  a.Mp = c->Mp;
+  a.pstride = c->Mp * c->Mp;
+  a.theta = theta;
+  a.beta = beta;
+  a.mu = mu;
+  a.out = c->D0p;
+  a.dg = c->dg0;
+  a.rD = c->rD0;
+  a.part = c->part;
+  HIPCHK(c, launch_init(c->opt.precision, a, c->stream));
+  int st = reduce(c, c->part, (int)(c->Mp / 64), 0, c->d20, c->dg0, nullptr, 0);
+  if (st != GCP_OK) return st;
+  HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->t1_0 = c->sc_host->t1;
+  c->t2_0 = c->sc_host->t2;
+  (void)vec;
+  c->inited = true;
+  return GCP_OK;
+}
+
+extern "C" int gcp_get_init_scalars(const gcp_ctx *c, double *mu, double *beta, double *emin,
+                                    double *emax) {
+  if (!c) return GCP_ERR_INVALID_ARG;
+  if (!c->inited) return GCP_ERR_STATE;
+  if (mu) *mu = c->mu;
+  if (beta) *beta = c->beta;
+  if (emin) *emin = c->emin;
+  if (emax) *emax = c->emax;
+  return GCP_OK;
+}
+
+extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_result *res) {
+  if (!c) return GCP_ERR_INVALID_ARG;
+  if (!c->inited) {
+    c->err = "gcp_purify: call gcp_init first";
+    return GCP_ERR_STATE;
+  }
+  if (!D || ldd < c->M || (dtype != GCP_DTYPE_F64 && dtype != GCP_DTYPE_F32)) {
+    c->err = "gcp_purify: need D != NULL, ldd >= M and dtype F64 or F32";
+    return GCP_ERR_INVALID_ARG;
+  }
+  const auto t_start = std::chrono::steady_clock::now();
+  const int prec = c->opt.precision;
+  const size_t vec = (size_t)c->Mp * sizeof(double);
+  const int64_t PS = c->Mp * c->Mp;
+  const int max_iter = c->opt.max_iter;
+
+  // start from D_0
+  c->cur = 0;
+  HIPCHK(c, hipMemcpyAsync(c->Dp[0], c->D0p, plane_bytes(c), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->dg[0], c->dg0, vec, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->rD[0], c->rD0, vec, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d2[0], c->d20, vec, hipMemcpyDeviceToDevice, c->stream));
+  Scalars s0{};
+  s0.t1 = c->t1_0;
+  s0.t2 = c->t2_0;
+  *c->sc_host = s0;
+  HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
+
+  const bool prof = c->opt.profile != 0;
+  const int max_launch = 2 * max_iter + 2;
+  if (prof && (int)c->events.size() < 2 * max_launch) {
+    for (int k = (int)c->events.size(); k < 2 * max_launch; ++k) {
+      hipEvent_t e;
+      HIPCHK(c, hipEventCreate(&e));
+      c->events.push_back(e);
+    }
+  }
+  int nlaunch = 0;
+  auto gemm = [&](GemmArgs &g) -> int {
+    if (prof) HIPCHK(c, hipEventRecord(c->events[2 * nlaunch], c->stream));
+    HIPCHK(c, launch_gemm(prec, g, c->stream));
+    if (prof) HIPCHK(c, hipEventRecord(c->events[2 * nlaunch + 1], c->stream));
+    ++nlaunch;
+    return GCP_OK;
+  };
+
+  GemmArgs g{};
+  g.Mp = c->Mp;
+  g.pstride = PS;
+  g.nt = c->nt;
+  g.fold = c->opt.fold_every;
+  g.part = c->part;
+  g.tpart = c->tpart;
+  g.s2 = c->s2;
+  g.d3 = c->d3;
+  g.coef = &c->sc->c;
+
+  int status = 0, n = 0;
+  for (;; ++n) {
+    const int k = c->cur;
+    // K1: X2 = D D
+    g.mode = 0;
+    g.A = c->Dp[k];
+    g.B = c->Dp[k];
+    g.out = c->X2p;
+    g.dg = c->dg[k];
+    g.rD = c->rD[k];
+    g.d2 = c->d2[k];
+    int st = gemm(g);
+    if (st != GCP_OK) return st;
+    st = reduce(c, c->part, c->nt, 1, c->d3, nullptr, c->tpart, n);
+    if (st != GCP_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    status = c->sc_host->status;
+    if (status != 0) break;
+    // K2: D_{n+1} = (1 - 2c) D + (2 + 2c) X2 - 2 X2 D
+    g.mode = 1;
+    g.A = c->X2p;
+    g.B = c->Dp[k];
+    g.out = c->Dp[1 - k];
+    g.dg_new = c->dg[1 - k];
+    g.rD_new = c->rD[1 - k];
+    st = gemm(g);
+    if (st != GCP_OK) return st;
+    st = reduce(c, c->part, c->nt, 2, c->d2[1 - k], c->dg[1 - k], c->tpart, n);
+    if (st != GCP_OK) return st;
+    c->cur = 1 - k;
+  }
+  const int iters = n;
+  // output D_p
+  OutArgs oa{};
+  oa.planes = c->Dp[c->cur];
+  oa.dg = c->dg[c->cur];
+  oa.M = c->M;
+  oa.Mp = c->Mp;
+  oa.pstride = PS;
+  oa.ldd = ldd;
+  oa.D = D;
+  oa.dtype = dtype;
+  HIPCHK(c, launch_output(prec, oa, c->stream));
+  c->hist_rows = iters + 1;
+  c->hist_host.assign((size_t)c->hist_rows * GCP_HIST_COLS, NAN);
+  HIPCHK(c, hipMemcpyAsync(c->hist_host.data(), c->hist,
+                           c->hist_host.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const auto t_end = std::chrono::steady_clock::now();
+
+  int rc = GCP_OK;
+  if (status == 2) rc = GCP_ERR_NOT_CONVERGED;
+  if (status == 3) rc = GCP_ERR_BREAKDOWN;
+  if (res) {
+    std::memset(res, 0, sizeof(*res));
+    res->status = rc;
+    res->iters = iters;
+    res->t1 = c->sc_host->t1;
+    res->t2 = c->sc_host->t2;
+    res->c_last = iters > 0 ? c->hist_host[(size_t)(iters - 1) * GCP_HIST_COLS + 4] : NAN;
+    res->idem = std::sqrt(c->sc_host->omega);
+    res->ms_total = std::chrono::duration<double, std::milli>(t_end - t_start).count();
+    res->gemm_launches = nlaunch;
+    const double Md = (double)c->M;
+    res->gemm_flops = (double)nlaunch * Md * Md * (Md + 1.0);
+    res->mfma_flops = (double)nlaunch * (double)c->ntiles * 2.0 * 128.0 * 128.0 *
+                      (double)c->Mp * (double)products(prec);
+    double ms = 0.0;
+    if (prof) {
+      for (int k = 0; k < nlaunch; ++k) {
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, c->events[2 * k], c->events[2 * k + 1]));
+        ms += t;
+      }
+    }
+    res->gemm_ms = ms;
+  }
+  if (rc != GCP_OK)
+    c->err = status == 2 ? "gcp_purify: max_iter reached before the tolerance"
+                         : "gcp_purify: breakdown (c outside [0,1], Tr(D Dbar) < 0 or non-finite)";
+  return rc;
+}
+
+extern "C" int gcp_get_history(const gcp_ctx *c, double *rows, int32_t max_rows,
+                               int32_t *n_rows) {
+  if (!c || !n_rows) return GCP_ERR_INVALID_ARG;
+  *n_rows = c->hist_rows;
+  if (rows) {
+    const int n = max_rows < c->hist_rows ? max_rows : c->hist_rows;
+    if (n > 0) std::memcpy(rows, c->hist_host.data(), (size_t)n * GCP_HIST_COLS * sizeof(double));
+  }
+  return GCP_OK;
+}

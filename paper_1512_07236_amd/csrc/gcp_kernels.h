@@ -1,0 +1,81 @@
+// gcp_kernels.h -- argument blocks and launchers shared by the host library
+// and the device kernels (internal; the public interface is include/gcp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gcp {
+
+// Device-resident scalars of one solve (FP64 traces and the decision).
+struct Scalars {
+  double t1, t2, t3, omega, c, step;
+  int32_t status;   // 0 continue, 1 converged, 2 max_iter reached, 3 breakdown
+  int32_t pad;
+  double hstat[4];  // Gershgorin min, max, Tr H
+};
+
+struct GemmArgs {
+  const void *A;       // left operand planes (rows of D or X2)
+  const void *B;       // right operand planes (rows of D)
+  void *out;           // output planes (X2 in mode 0, D_{n+1} in mode 1)
+  int64_t Mp;          // padded size (multiple of 128)
+  int64_t pstride;     // elements between planes
+  int nt;              // Mp / 128
+  int mode;            // 0: X2 = D D, 1: D_{n+1} = (1-2c) D + (2+2c) X2 - 2 X2 D
+  int fold;            // fold period of the main accumulator, in K stages
+  int pad;
+  const double *dg;    // diag(D) FP64
+  const double *rD;    // diag(D) - dec(enc(diag(D)))
+  const double *d2;    // diag(X2) FP64
+  double *s2;          // diag(X2) - dec(enc(diag(X2)))   (written in mode 0)
+  const double *d3;    // diag(X2 D) FP64                 (mode 1)
+  double *dg_new;      // diag(D_{n+1})                   (mode 1)
+  double *rD_new;      // its residual                    (mode 1)
+  double *part;        // row sums [nt][Mp]
+  double *tpart;       // tile sums [ntiles]
+  const double *coef;  // coef[0] = c_n (mode 1)
+};
+
+struct InitArgs {
+  const double *H;
+  int64_t ldh, M, Mp, pstride;
+  double theta, beta, mu;
+  void *out;
+  double *dg, *rD, *part;
+};
+
+struct RedArgs {
+  const double *part;
+  int nslots;
+  int mode;            // 0 after init, 1 after D^2, 2 after the update
+  int64_t Mp;
+  double *out;
+  const double *extra;
+  double *bpart;
+  unsigned *counter;
+  const double *tpart;
+  int ntiles;
+  int iter, max_iter;
+  int pad;
+  double tol_ddbar, tol_idem, N;
+  Scalars *sc;
+  double *hist;
+};
+
+struct OutArgs {
+  const void *planes;
+  const double *dg;
+  int64_t M, Mp, pstride, ldd;
+  void *D;
+  int dtype;
+};
+
+hipError_t launch_gemm(int prec, const GemmArgs &g, hipStream_t st);
+hipError_t launch_init(int prec, const InitArgs &a, hipStream_t st);
+hipError_t launch_output(int prec, const OutArgs &a, hipStream_t st);
+hipError_t launch_reduce(const RedArgs &a, hipStream_t st);
+hipError_t launch_hstats(const double *H, int64_t ldh, int64_t M, double *lo, double *hi,
+                         double *hd, double *out, hipStream_t st);
+
+}  // namespace gcp

@@ -1,0 +1,646 @@
+// gcp_kernels.hip -- device kernels of the purification path (gfx950 / CDNA4).
+//
+// One purification iteration (eq. (hpcp3) expanded with Dbar = I - D):
+//   D_{n+1} = (1 - 2c) D + (2 + 2c) D^2 - 2 D^3,   c = (T2 - T3) / (T1 - T2),
+//   T_k = Tr D^k.
+// It is two symmetric matrix products, each an MFMA GEMM over the upper
+// triangle of 128 x 128 output tiles (results mirrored):
+//   K1 (mode 0):  X2 = D D        epilogue: store X2, row sums of X2 o D
+//                                 (diag of D^3) and ||X2 - D||_F^2
+//   K2 (mode 1):  X3 = X2 D       epilogue: D_{n+1} from D, X2 and X3 (X3 never
+//                                 stored), row sums of D_{n+1} o D_{n+1} (diag
+//                                 of D_{n+1}^2) and ||D_{n+1} - D_n||_F^2
+// Both are A * B^T products of row panels (all iterates are symmetric), so
+// both operands are read along contiguous K.  Row sums go to a [slot][row]
+// FP64 buffer (one writer per slot) and a reduction kernel adds them in a
+// fixed order: every trace, and therefore c_n, is bitwise reproducible.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gcp_encode.h"
+#include "gcp_kernels.h"
+
+namespace gcp {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __bf16 v8b __attribute__((ext_vector_type(8)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
+constexpr int TILE = 128;   // output tile edge
+constexpr int NTH = 256;    // threads per tile: 4 waves in a 2 x 2 grid of 64 x 64
+
+template <int KIND> struct AccType { using type = v4f; };
+template <> struct AccType<0> { using type = v4d; };
+
+// 16x16 output block per MFMA; lane l holds column l%16 and four rows r = 0..3:
+// rows 4*(l/16)+r for the FP32-accumulating instructions, rows (l/16)+4r for
+// the FP64 one.  A/B fragments: lane l supplies row l%16 of its operand at K
+// offsets determined by l/16 (the same for A and B, so the K order inside an
+// instruction never matters).
+template <int KIND>
+__device__ __forceinline__ int acc_row(int lg, int r) {
+  return KIND == 0 ? lg + 4 * r : 4 * lg + r;
+}
+__device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <int KIND>
+__device__ __forceinline__ v4f mfma16(v4u a, v4u b, v4f c) {
+  if constexpr (KIND == 2)
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8b, a),
+                                                   __builtin_bit_cast(v8b, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a),
+                                                  __builtin_bit_cast(v8h, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
+
+// Upper-triangle tile of block b.  Blocks are dispatched round-robin over the
+// 8 XCDs; each XCD gets a contiguous run of the row-major triangle order so
+// that the tiles resident on one XCD share row panels in its L2.
+__device__ __forceinline__ void tile_of_block(int b, int nt, int &ti, int &tj, int &lin) {
+  const int ntiles = nt * (nt + 1) / 2;
+  const int xcd = b & 7, loc = b >> 3, q = ntiles >> 3, r = ntiles & 7;
+  int L = xcd * q + (xcd < r ? xcd : r) + loc;
+  lin = L;
+  int t = 0, len = nt;
+  while (L >= len) { L -= len; ++t; --len; }
+  ti = t;
+  tj = t + L;
+}
+
+// Two tiles per CU when the accumulators fit in 256 registers; the folded and
+// 3-plane variants need the full 512-entry register file (one tile per CU).
+template <int P, bool FOLD>
+constexpr int gemm_min_blocks() { return (FOLD || Enc<P>::NP == 3) ? 1 : 2; }
+
+template <int P, bool FOLD>
+__global__ __launch_bounds__(NTH, (gemm_min_blocks<P, FOLD>())) void k_gemm(GemmArgs g) {
+  using E = Enc<P>;
+  using T = typename E::T;
+  constexpr int NP = E::NP, KIND = E::KIND;
+  constexpr int ES = sizeof(T);
+  constexpr int KT = (ES == 2) ? 32 : 128 / ES;   // K per LDS stage
+  constexpr int EPC = 16 / ES;                    // elements per 16-byte chunk
+  constexpr int LDR = KT + EPC;                   // LDS row stride (one chunk of padding)
+  constexpr int CPR = KT / EPC;                   // chunks per row per plane
+  constexpr int CPT = TILE * CPR / NTH;           // chunks per thread per operand per plane
+  using Acc = typename AccType<KIND>::type;
+
+  __shared__ __attribute__((aligned(16))) T smem[2 * NP * TILE * LDR];
+
+  int ti, tj, lin;
+  tile_of_block(blockIdx.x, g.nt, ti, tj, lin);
+  const int64_t Mp = g.Mp, PS = g.pstride;
+  const int64_t arow0 = (int64_t)ti * TILE, brow0 = (int64_t)tj * TILE;
+  const T *__restrict__ Ag = (const T *)g.A;
+  const T *__restrict__ Bg = (const T *)g.B;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1, l16 = lane & 15, lg = lane >> 4;
+
+  T *As = smem;
+  T *Bs = smem + NP * TILE * LDR;
+
+  v4u ra[NP][CPT], rb[NP][CPT];
+  auto gload = [&](int kt) {
+    const int64_t k0 = (int64_t)kt * KT;
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int ch = tid + c * NTH, row = ch / CPR, kc = ch % CPR;
+        ra[p][c] = *(const v4u *)(Ag + p * PS + (arow0 + row) * Mp + k0 + kc * EPC);
+        rb[p][c] = *(const v4u *)(Bg + p * PS + (brow0 + row) * Mp + k0 + kc * EPC);
+      }
+  };
+  auto swrite = [&]() {
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int c = 0; c < CPT; ++c) {
+        const int ch = tid + c * NTH, row = ch / CPR, kc = ch % CPR;
+        *(v4u *)(As + (p * TILE + row) * LDR + kc * EPC) = ra[p][c];
+        *(v4u *)(Bs + (p * TILE + row) * LDR + kc * EPC) = rb[p][c];
+      }
+  };
+
+  Acc acc0[4][4], acc1[4][4], tot[4][4];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+      acc0[bi][bj] = Acc{};
+      acc1[bi][bj] = Acc{};
+      tot[bi][bj] = Acc{};
+    }
+
+  const int nk = (int)(Mp / KT);
+  gload(0);
+  swrite();
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    if (kt + 1 < nk) gload(kt + 1);
+    if constexpr (KIND >= 2) {
+      v4u bf[NP][4];
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+          bf[p][bj] = *(const v4u *)(Bs + (p * TILE + wn * 64 + bj * 16 + l16) * LDR + lg * 8);
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi) {
+        v4u af[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+          af[p] = *(const v4u *)(As + (p * TILE + wm * 64 + bi * 16 + l16) * LDR + lg * 8);
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+          acc0[bi][bj] = mfma16<KIND>(af[0], bf[0][bj], acc0[bi][bj]);
+          if constexpr (NP >= 2) {
+            acc1[bi][bj] = mfma16<KIND>(af[0], bf[1][bj], acc1[bi][bj]);
+            acc1[bi][bj] = mfma16<KIND>(af[1], bf[0][bj], acc1[bi][bj]);
+          }
+          if constexpr (NP == 3) {
+            acc1[bi][bj] = mfma16<KIND>(af[1], bf[1][bj], acc1[bi][bj]);
+            acc1[bi][bj] = mfma16<KIND>(af[0], bf[2][bj], acc1[bi][bj]);
+            acc1[bi][bj] = mfma16<KIND>(af[2], bf[0][bj], acc1[bi][bj]);
+          }
+        }
+      }
+      if constexpr (FOLD) {
+        if ((kt + 1) % g.fold == 0) {
+#pragma unroll
+          for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj) {
+              tot[bi][bj] += acc0[bi][bj];
+              acc0[bi][bj] = Acc{};
+            }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < KT / 4; ++ks) {
+        T bf[4];
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) bf[bj] = Bs[(wn * 64 + bj * 16 + l16) * LDR + ks * 4 + lg];
+#pragma unroll
+        for (int bi = 0; bi < 4; ++bi) {
+          const T af = As[(wm * 64 + bi * 16 + l16) * LDR + ks * 4 + lg];
+#pragma unroll
+          for (int bj = 0; bj < 4; ++bj) acc0[bi][bj] = mfma(af, bf[bj], acc0[bi][bj]);
+        }
+      }
+    }
+    __syncthreads();
+    if (kt + 1 < nk) {
+      swrite();
+      __syncthreads();
+    }
+  }
+
+  // ------------------------------------------------------------ epilogue
+  const double S = E::PROD_SCALE;
+  const bool diag_tile = (ti == tj);
+  T *__restrict__ Og = (T *)g.out;
+  double rowacc[4][4], colacc[4], tacc = 0.0;
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi) {
+    colacc[bi] = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rowacc[bi][r] = 0.0;
+  }
+  double a_coef = 0.0, b_coef = 0.0;
+  if (g.mode == 1) {
+    const double c = g.coef[0];
+    a_coef = 1.0 - 2.0 * c;
+    b_coef = 2.0 + 2.0 * c;
+  }
+
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = arow0 + wm * 64 + bi * 16 + acc_row<KIND>(lg, r);
+        const int64_t j = brow0 + wn * 64 + bj * 16 + l16;
+        if (diag_tile && i > j) continue;   // covered by the mirror of (j, i)
+        double v = (double)tot[bi][bj][r] + (double)acc0[bi][bj][r];
+        if constexpr (NP >= 2) v += (double)acc1[bi][bj][r];
+        v *= S;
+        T dp[NP], op[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) dp[p] = Bg[p * PS + i * Mp + j];   // D(i, j)
+        double prod, diff;
+        if (g.mode == 0) {
+          // X2 = (D_enc + diag(rD))^2: exact diagonal-residual correction
+          double Dm, x2;
+          if (i == j) {
+            Dm = g.dg[i];
+            x2 = g.d2[i];
+          } else {
+            Dm = E::dec(dp);
+            x2 = v + Dm * (g.rD[i] + g.rD[j]);
+          }
+          E::enc(x2, op);
+          const double x2m = (i == j) ? x2 : E::dec(op);
+          if (i == j) g.s2[i] = x2 - E::dec(op);
+          prod = x2m * Dm;
+          diff = x2m - Dm;
+        } else {
+          double Dm, dn;
+          if (i == j) {
+            Dm = g.dg[i];
+            dn = a_coef * Dm + b_coef * g.d2[i] - 2.0 * g.d3[i];
+          } else {
+            T xp[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) xp[p] = Ag[p * PS + i * Mp + j];   // X2(i, j)
+            Dm = E::dec(dp);
+            const double X2m = E::dec(xp);
+            // X3 = (X2_enc + diag(s2)) (D_enc + diag(rD))
+            const double x3 = v + X2m * g.rD[j] + g.s2[i] * Dm;
+            dn = a_coef * Dm + b_coef * X2m - 2.0 * x3;
+          }
+          E::enc(dn, op);
+          const double dnm = (i == j) ? dn : E::dec(op);
+          if (i == j) {
+            g.dg_new[i] = dn;
+            g.rD_new[i] = dn - E::dec(op);
+          }
+          prod = dnm * dnm;
+          diff = dnm - Dm;
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          Og[p * PS + i * Mp + j] = op[p];
+          if (i != j) Og[p * PS + j * Mp + i] = op[p];
+        }
+        rowacc[bi][r] += prod;
+        if (i != j) {
+          colacc[bj] += prod;
+          tacc += 2.0 * diff * diff;
+        } else {
+          tacc += diff * diff;
+        }
+      }
+
+  // lane reductions (fixed order): rows over the 16 lanes of a column group,
+  // columns over the 4 row groups, the tile scalar over the wave
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double v = rowacc[bi][r];
+      v += shfl_xor_d(v, 1);
+      v += shfl_xor_d(v, 2);
+      v += shfl_xor_d(v, 4);
+      v += shfl_xor_d(v, 8);
+      rowacc[bi][r] = v;
+    }
+#pragma unroll
+  for (int bj = 0; bj < 4; ++bj) {
+    double v = colacc[bj];
+    v += shfl_xor_d(v, 16);
+    v += shfl_xor_d(v, 32);
+    colacc[bj] = v;
+  }
+  tacc += shfl_xor_d(tacc, 1);
+  tacc += shfl_xor_d(tacc, 2);
+  tacc += shfl_xor_d(tacc, 4);
+  tacc += shfl_xor_d(tacc, 8);
+  tacc += shfl_xor_d(tacc, 16);
+  tacc += shfl_xor_d(tacc, 32);
+
+  double *rp = (double *)smem;    // [2 (wn)][128 rows]
+  double *cp = rp + 2 * TILE;     // [2 (wm)][128 cols]
+  double *tp = cp + 2 * TILE;     // [4 waves]
+  __syncthreads();                // main-loop LDS no longer in use
+  if (l16 == 0) {
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        rp[wn * TILE + wm * 64 + bi * 16 + acc_row<KIND>(lg, r)] = rowacc[bi][r];
+  }
+  if (lg == 0) {
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) cp[wm * TILE + wn * 64 + bj * 16 + l16] = colacc[bj];
+  }
+  if (lane == 0) tp[wave] = tacc;
+  __syncthreads();
+  if (tid < TILE) {
+    const double rs = rp[tid] + rp[TILE + tid];
+    const double cs = cp[tid] + cp[TILE + tid];
+    if (!diag_tile) {
+      g.part[(int64_t)tj * Mp + arow0 + tid] = rs;
+      g.part[(int64_t)ti * Mp + brow0 + tid] = cs;
+    } else {
+      g.part[(int64_t)ti * Mp + arow0 + tid] = rs + cs;
+    }
+  }
+  if (tid == 0) g.tpart[lin] = ((tp[0] + tp[1]) + tp[2]) + tp[3];
+}
+
+// ------------------------------------------------------------------ H stats
+// Per row: H_ii and the Gershgorin radius r_i = sum_{j != i} |H_ij|.
+__global__ __launch_bounds__(256) void k_hstats(const double *__restrict__ H, int64_t ldh,
+                                                int64_t M, double *lo, double *hi,
+                                                double *hd) {
+  __shared__ double red[256];
+  const int64_t i = blockIdx.x;
+  double s = 0.0;
+  for (int64_t j = threadIdx.x; j < M; j += 256)
+    if (j != i) s += fabs(H[i * ldh + j]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double d = H[i * ldh + i];
+    lo[i] = d - red[0];
+    hi[i] = d + red[0];
+    hd[i] = d;
+  }
+}
+
+// Single block: min of lo, max of hi and the (fixed-order) sum of hd.
+__global__ __launch_bounds__(256) void k_hfinal(const double *lo, const double *hi,
+                                                const double *hd, int64_t M, double *out) {
+  __shared__ double smin[256], smax[256], ssum[256];
+  double mn = INFINITY, mx = -INFINITY, sm = 0.0;
+  for (int64_t i = threadIdx.x; i < M; i += 256) {
+    mn = fmin(mn, lo[i]);
+    mx = fmax(mx, hi[i]);
+    sm += hd[i];
+  }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  ssum[threadIdx.x] = sm;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + w]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+      ssum[threadIdx.x] += ssum[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = smin[0];
+    out[1] = smax[0];
+    out[2] = ssum[0];
+  }
+}
+
+// ------------------------------------------------------------ initial guess
+// D0 = theta I + beta (mu I - (H + H^T)/2) over 64 x 64 tiles of the padded
+// matrix; writes the operand planes, the FP64 diagonal (dg, rD) and row sums
+// of D0 o D0 into part[tile column][row] (the diagonal of D0^2).
+template <int P>
+__global__ __launch_bounds__(256) void k_init(InitArgs a) {
+  using E = Enc<P>;
+  using T = typename E::T;
+  constexpr int NP = E::NP;
+  __shared__ double hs[64][65], ht[64][65];
+  const int64_t I = (int64_t)blockIdx.y * 64, J = (int64_t)blockIdx.x * 64;
+  const int tid = threadIdx.x, row = tid >> 2, c0 = (tid & 3) * 16;
+  // hs[row][c] = H[I+row][J+c], ht[row][c] = H[J+row][I+c]
+#pragma unroll 4
+  for (int c = 0; c < 16; ++c) {
+    const int64_t gi = I + row, gj = J + c0 + c;
+    hs[row][c0 + c] = (gi < a.M && gj < a.M) ? a.H[gi * a.ldh + gj] : 0.0;
+    const int64_t ti = J + row, tj = I + c0 + c;
+    ht[row][c0 + c] = (ti < a.M && tj < a.M) ? a.H[ti * a.ldh + tj] : 0.0;
+  }
+  __syncthreads();
+  T *__restrict__ Og = (T *)a.out;
+  double rsum = 0.0;
+  for (int c = 0; c < 16; ++c) {
+    const int64_t i = I + row, j = J + c0 + c;
+    double x = 0.0;
+    if (i < a.M && j < a.M) {
+      const double h = 0.5 * (hs[row][c0 + c] + ht[c0 + c][row]);
+      x = -a.beta * h;
+      if (i == j) x += a.theta + a.beta * a.mu;
+    }
+    T op[NP];
+    E::enc(x, op);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) Og[p * a.pstride + i * a.Mp + j] = op[p];
+    const double xm = (i == j) ? x : E::dec(op);
+    if (i == j) {
+      a.dg[i] = x;
+      a.rD[i] = x - E::dec(op);
+    }
+    rsum += xm * xm;
+  }
+  rsum += __shfl_xor(rsum, 1, 64);
+  rsum += __shfl_xor(rsum, 2, 64);
+  if ((tid & 3) == 0) a.part[(int64_t)blockIdx.x * a.Mp + I + row] = rsum;
+}
+
+// -------------------------------------------------------------- reductions
+// out[i] = sum_s part[s][i] (s ascending); per-block sums of out and of
+// extra; the last block to finish adds the block sums and the tile partials
+// in a fixed order and runs the scalar step for this point of the iteration.
+__device__ __forceinline__ double ld_agent(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
+  __shared__ double s1[256], s2[256], s3[256];
+  __shared__ int is_last;
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+  double v = 0.0, e = 0.0;
+  if (i < a.Mp) {
+    for (int s = 0; s < a.nslots; ++s) v += a.part[(int64_t)s * a.Mp + i];
+    a.out[i] = v;
+    if (a.extra) e = a.extra[i];
+  }
+  s1[tid] = v;
+  s2[tid] = e;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      s1[tid] += s1[tid + w];
+      s2[tid] += s2[tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    a.bpart[2 * blockIdx.x] = s1[0];
+    a.bpart[2 * blockIdx.x + 1] = s2[0];
+    __threadfence();
+    const unsigned ticket = atomicAdd(a.counter, 1u);
+    is_last = (ticket == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  double b1 = 0.0, b2 = 0.0, b3 = 0.0;
+  for (int b = tid; b < (int)gridDim.x; b += 256) {
+    b1 += ld_agent(a.bpart + 2 * b);
+    b2 += ld_agent(a.bpart + 2 * b + 1);
+  }
+  if (a.tpart)
+    for (int t = tid; t < a.ntiles; t += 256) b3 += a.tpart[t];
+  s1[tid] = b1;
+  s2[tid] = b2;
+  s3[tid] = b3;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      s1[tid] += s1[tid + w];
+      s2[tid] += s2[tid + w];
+      s3[tid] += s3[tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid != 0) return;
+  *a.counter = 0u;
+  Scalars *sc = a.sc;
+  const double sum_out = s1[0], sum_extra = s2[0], sum_tiles = s3[0];
+  if (a.mode == 0) {            // after the initial guess
+    sc->t2 = sum_out;
+    sc->t1 = sum_extra;
+  } else if (a.mode == 1) {     // after D^2: decide and form c
+    const double t1 = sc->t1, t2 = sc->t2, t3 = sum_out, om = sum_tiles;
+    const double ddbar = t1 - t2;
+    int status = 0;
+    double c = NAN;
+    if (!isfinite(t1) || !isfinite(t2) || !isfinite(om)) {
+      status = 3;
+    } else if (fabs(ddbar) <= a.tol_ddbar || sqrt(om) <= a.tol_idem) {
+      status = 1;
+    } else if (a.iter >= a.max_iter) {
+      status = 2;
+    } else if (ddbar <= 0.0) {
+      status = 3;
+    } else {
+      c = (t2 - t3) / ddbar;
+      if (!isfinite(c) || c < 0.0 || c > 1.0) status = 3;
+    }
+    sc->t3 = t3;
+    sc->omega = om;
+    sc->c = c;
+    sc->status = status;
+    double *h = a.hist + (int64_t)a.iter * 9;
+    const double gamma = 1.0 / 3.0 - 2.0 / 3.0 * c;
+    h[0] = a.iter; h[1] = t1; h[2] = t2; h[5] = om;
+    if (status == 0) {
+      h[3] = t3; h[4] = c; h[6] = gamma;
+      h[7] = om - gamma * (3.0 * t2 - 2.0 * t3 - a.N);
+    } else {
+      h[3] = h[4] = h[6] = h[7] = NAN;
+    }
+    h[8] = NAN;
+  } else {                      // after the update: traces of D_{n+1}
+    sc->t2 = sum_out;
+    sc->t1 = sum_extra;
+    sc->step = sum_tiles;
+    a.hist[(int64_t)a.iter * 9 + 8] = sqrt(sum_tiles);
+  }
+}
+
+// ------------------------------------------------------------------ output
+template <int P>
+__global__ __launch_bounds__(256) void k_output(OutArgs a) {
+  using E = Enc<P>;
+  using T = typename E::T;
+  constexpr int NP = E::NP;
+  const int64_t i = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.M || j >= a.M) return;
+  double x;
+  if (i == j) {
+    x = a.dg[i];
+  } else {
+    T p[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) p[q] = ((const T *)a.planes)[q * a.pstride + i * a.Mp + j];
+    x = E::dec(p);
+  }
+  if (a.dtype == GCP_DTYPE_F64)
+    ((double *)a.D)[i * a.ldd + j] = x;
+  else
+    ((float *)a.D)[i * a.ldd + j] = (float)x;
+}
+
+// ---------------------------------------------------------------- dispatch
+template <int P>
+static hipError_t launch_gemm_p(const GemmArgs &g, int ntiles, hipStream_t st) {
+  if (g.fold > 0 && Enc<P>::KIND >= 2 && Enc<P>::NP >= 2)
+    k_gemm<P, true><<<ntiles, NTH, 0, st>>>(g);
+  else
+    k_gemm<P, false><<<ntiles, NTH, 0, st>>>(g);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(int prec, const GemmArgs &g, hipStream_t st) {
+  const int ntiles = g.nt * (g.nt + 1) / 2;
+  switch (prec) {
+    case GCP_FP64: return launch_gemm_p<GCP_FP64>(g, ntiles, st);
+    case GCP_FP32: return launch_gemm_p<GCP_FP32>(g, ntiles, st);
+    case GCP_BF16: return launch_gemm_p<GCP_BF16>(g, ntiles, st);
+    case GCP_FP16: return launch_gemm_p<GCP_FP16>(g, ntiles, st);
+    case GCP_BF16X3: return launch_gemm_p<GCP_BF16X3>(g, ntiles, st);
+    case GCP_FP16X3: return launch_gemm_p<GCP_FP16X3>(g, ntiles, st);
+    case GCP_BF16X6: return launch_gemm_p<GCP_BF16X6>(g, ntiles, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_init(int prec, const InitArgs &a, hipStream_t st) {
+  const dim3 grid((unsigned)(a.Mp / 64), (unsigned)(a.Mp / 64));
+  switch (prec) {
+    case GCP_FP64: k_init<GCP_FP64><<<grid, 256, 0, st>>>(a); break;
+    case GCP_FP32: k_init<GCP_FP32><<<grid, 256, 0, st>>>(a); break;
+    case GCP_BF16: k_init<GCP_BF16><<<grid, 256, 0, st>>>(a); break;
+    case GCP_FP16: k_init<GCP_FP16><<<grid, 256, 0, st>>>(a); break;
+    case GCP_BF16X3: k_init<GCP_BF16X3><<<grid, 256, 0, st>>>(a); break;
+    case GCP_FP16X3: k_init<GCP_FP16X3><<<grid, 256, 0, st>>>(a); break;
+    case GCP_BF16X6: k_init<GCP_BF16X6><<<grid, 256, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_output(int prec, const OutArgs &a, hipStream_t st) {
+  const dim3 grid((unsigned)((a.M + 255) / 256), (unsigned)a.M);
+  switch (prec) {
+    case GCP_FP64: k_output<GCP_FP64><<<grid, 256, 0, st>>>(a); break;
+    case GCP_FP32: k_output<GCP_FP32><<<grid, 256, 0, st>>>(a); break;
+    case GCP_BF16: k_output<GCP_BF16><<<grid, 256, 0, st>>>(a); break;
+    case GCP_FP16: k_output<GCP_FP16><<<grid, 256, 0, st>>>(a); break;
+    case GCP_BF16X3: k_output<GCP_BF16X3><<<grid, 256, 0, st>>>(a); break;
+    case GCP_FP16X3: k_output<GCP_FP16X3><<<grid, 256, 0, st>>>(a); break;
+    case GCP_BF16X6: k_output<GCP_BF16X6><<<grid, 256, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_hstats(const double *H, int64_t ldh, int64_t M, double *lo, double *hi,
+                         double *hd, double *out, hipStream_t st) {
+  k_hstats<<<(unsigned)M, 256, 0, st>>>(H, ldh, M, lo, hi, hd);
+  k_hfinal<<<1, 256, 0, st>>>(lo, hi, hd, M, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const RedArgs &a, hipStream_t st) {
+  k_reduce<<<(unsigned)((a.Mp + 255) / 256), 256, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace gcp
