@@ -31,6 +31,10 @@ ERR_TOL = {"fp64": 1e-11, "fp32": 2e-6, "fp16x3": 1e-6, "bf16x6": 1e-6, "bf16x3"
            "fp16": 3e-3, "bf16": 3e-2}
 
 
+TOL_DDBAR = {"fp64": 1e-9, "fp32": 1e-6, "fp16x3": 1e-6, "bf16x6": 1e-6, "bf16x3": 2e-5,
+             "fp16": 2e-3, "bf16": 5e-2}
+
+
 def log(msg):
     print(msg, flush=True)
     sys.stdout.flush()
@@ -68,8 +72,11 @@ def test_fp64_chain_matches_oracle_step_by_step():
     assert res.iters == ref.iters
     h = res.history
     assert h.shape[0] == ref.iters + 1
+    # c_n = (T2 - T3)/(T1 - T2): the traces agree to FP64 rounding of sums of
+    # size ~N, so c_n agrees to that over Tr(D Dbar)
     ddbar = ref.col("t1")[:-1] - ref.col("t2")[:-1]
-    assert np.all(np.abs(res.col("c")[:-1] - ref.col("c")[:-1]) <= 1e-12 + 1e-14 / np.abs(ddbar))
+    ctol = 1e-12 + 1e-14 * w.N / np.abs(ddbar)
+    assert np.all(np.abs(res.col("c")[:-1] - ref.col("c")[:-1]) <= ctol)
     assert np.abs(res.col("t1") - w.N).max() < 1e-10
     assert np.abs(res.col("t2") - ref.col("t2")).max() < 1e-10
     assert np.abs(D - ref.D).max() < 1e-12
@@ -96,9 +103,13 @@ def test_fp64_lagrangian_history_matches_oracle():
     ref = oracle.purify(w.H, w.N, w.emin, w.emax, tol_ddbar=1e-8)
     _, res = run_gpu(w, "fp64", tol_ddbar=1e-8)
     assert res.iters == ref.iters
-    for name in ("t3", "omega", "gamma", "lagrangian", "step"):
+    ddbar = np.abs(ref.col("t1") - ref.col("t2"))[:-1]
+    ctol = 1e-12 + 1e-14 * w.N / ddbar
+    for name in ("c", "gamma"):
+        assert np.all(np.abs(res.col(name)[:-1] - ref.col(name)[:-1]) <= ctol), name
+    for name in ("t3", "omega", "lagrangian", "step"):
         a, b = res.col(name)[:-1], ref.col(name)[:-1]
-        assert np.allclose(a, b, rtol=1e-9, atol=1e-11), name
+        assert np.allclose(a, b, rtol=1e-9, atol=1e-11 + 1e-14 * w.N), name
 
 
 # --------------------------------------------------------- every precision
@@ -109,7 +120,9 @@ def test_precisions_trace_exact_and_error_bounded(precision):
     the result within the precision's error bound of the definition, and the
     same iteration count as the eigenvalue map (high-precision modes)."""
     w = workloads.spectral(640, 234, gap=0.1, seed=33)
-    tol = {"fp64": 1e-9}.get(precision, 1e-6)
+    # stop above each encoding's noise floor of Tr(D Dbar): below it c_n is
+    # rounding noise and leaves [0, 1] (reported as a breakdown)
+    tol = TOL_DDBAR[precision]
     D, res = run_gpu(w, precision, tol_ddbar=tol)
     assert res.status == gcp.OK, res
     assert np.abs(res.col("t1") - w.N).max() < 1e-10
@@ -127,8 +140,8 @@ def test_fold_accumulation_matches_unfolded(precision):
     """Folding the FP32 accumulator changes only rounding."""
     w = workloads.spectral(512, 200, gap=0.1, seed=5)
     ref = oracle.projector_from_spectrum(w.Q, w.lam, w.N)
-    D0, r0 = run_gpu(w, precision, tol_ddbar=1e-6)
-    D1, r1 = run_gpu(w, precision, tol_ddbar=1e-6, fold_every=8)
+    D0, r0 = run_gpu(w, precision, tol_ddbar=TOL_DDBAR[precision])
+    D1, r1 = run_gpu(w, precision, tol_ddbar=TOL_DDBAR[precision], fold_every=8)
     assert r0.status == r1.status == gcp.OK
     e0, e1 = rel_err(D0, ref), rel_err(D1, ref)
     log(f"  {precision}: unfolded {e0:.3e} folded {e1:.3e}")
