@@ -81,9 +81,11 @@ typedef struct {
     int32_t max_iter;    /* maximum number of updates (default 100) */
     double tol_ddbar;    /* stop when |Tr(D Dbar)| <= tol_ddbar (default 1e-6, the paper's) */
     double tol_idem;     /* stop when ||D^2 - D||_F <= tol_idem (default 0 = off) */
-    int32_t fold_every;  /* 16-bit encodings: fold the FP32 main accumulator into a
-                            second FP32 total every fold_every*32 columns of K
-                            (0 = never; shortens the rounding chain, costs registers) */
+    int32_t fold_every;  /* 16-bit encodings: add the FP32 chunk accumulator into a
+                            second FP32 total every fold_every*32 columns of K.
+                            0 (default) = sqrt(K/32 / products), which minimises
+                            the accumulated rounding, the dominant error of the
+                            split encodings at large M; a value >= K/32 never folds. */
     int32_t profile;     /* 1: time every matrix-product launch with HIP events */
 } gcp_options;
 
@@ -108,10 +110,10 @@ typedef struct {
 int gcp_options_default(gcp_options *opt);
 
 /* Creates a context for M x M problems on the current device and the given
- * stream and allocates its device workspace (about 3 M^2 operand-encoding
- * elements plus O(M^2 / 128) FP64 partial sums).  M >= 1; M is padded
- * internally to a multiple of 128 with zero rows/columns (exact: the padding
- * is an invariant zero block).  *ctx is set to NULL on failure. */
+ * stream and allocates its device workspace (four copies of the operand
+ * encoding of an M x M matrix plus O(M^2 / 64) FP64 partial sums).  M >= 1;
+ * M is padded internally to a multiple of 256 with zero rows/columns (exact:
+ * the padding is an invariant zero block).  *ctx is set to NULL on failure. */
 int gcp_create(gcp_ctx **ctx, int64_t M, const gcp_options *opt, void *stream);
 
 /* Releases the context and its workspace (NULL is accepted). */

@@ -50,7 +50,7 @@ int products(int prec) {
 
 struct gcp_ctx {
   int64_t M = 0, Mp = 0;
-  int nt = 0, ntiles = 0, nred = 0;
+  int nt = 0, ntiles = 0, ntpart = 0, nred = 0;
   gcp_options opt{};
   hipStream_t stream = nullptr;
   int device = 0;
@@ -146,9 +146,12 @@ extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void
     return GCP_ERR_NO_MEMORY;
   }
   c->M = M;
-  c->Mp = (M + 127) / 128 * 128;
+  c->Mp = (M + 255) / 256 * 256;   // whole pairs of 128-wide tiles
   c->nt = (int)(c->Mp / 128);
   c->ntiles = c->nt * (c->nt + 1) / 2;
+  // tile partial sums: one per upper tile (FP64/FP32 kernel) or two per
+  // tile pair (16-bit kernel, zero for the half of a pair below the diagonal)
+  c->ntpart = elem_size(o.precision) == 2 ? 2 * pair_count(c->nt) : c->ntiles;
   c->nred = (int)((c->Mp + 255) / 256);
   c->opt = o;
   c->stream = (hipStream_t)stream;
@@ -181,7 +184,7 @@ extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void
   alloc((void **)&c->rD0, vec);
   alloc((void **)&c->d20, vec);
   alloc((void **)&c->part, (size_t)nslots_max * vec);
-  alloc((void **)&c->tpart, (size_t)c->ntiles * sizeof(double));
+  alloc((void **)&c->tpart, (size_t)c->ntpart * sizeof(double));
   alloc((void **)&c->bpart, (size_t)2 * c->nred * sizeof(double));
   alloc((void **)&c->hvec, 3 * vec);
   alloc((void **)&c->counter, sizeof(unsigned));
@@ -230,7 +233,7 @@ static int reduce(gcp_ctx *c, const double *part, int nslots, int mode, double *
   a.bpart = c->bpart;
   a.counter = c->counter;
   a.tpart = tpart;
-  a.ntiles = c->ntiles;
+  a.ntiles = c->ntpart;
   a.iter = iter;
   a.max_iter = c->opt.max_iter;
   a.tol_ddbar = c->opt.tol_ddbar;
@@ -370,7 +373,13 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
   g.Mp = c->Mp;
   g.pstride = PS;
   g.nt = c->nt;
-  g.fold = c->opt.fold_every;
+  // fold period of the 16-bit kernel: sqrt(K steps / products) unless given
+  {
+    const double steps = (double)(c->Mp / 32);
+    int f = c->opt.fold_every;
+    if (f <= 0) f = (int)std::lround(std::sqrt(steps / (double)products(prec)));
+    g.fold = f < 1 ? 1 : f;
+  }
   g.part = c->part;
   g.tpart = c->tpart;
   g.s2 = c->s2;

@@ -72,6 +72,8 @@ struct OutArgs {
 };
 
 hipError_t launch_gemm(int prec, const GemmArgs &g, hipStream_t st);
+// Blocks of the 16-bit product kernel (pairs of 128 x 128 tiles) for nt tiles per side.
+int pair_count(int nt);
 hipError_t launch_init(int prec, const InitArgs &a, hipStream_t st);
 hipError_t launch_output(int prec, const OutArgs &a, hipStream_t st);
 hipError_t launch_reduce(const RedArgs &a, hipStream_t st);

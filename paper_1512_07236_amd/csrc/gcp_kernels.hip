@@ -61,32 +61,47 @@ __device__ __forceinline__ v4f mfma16(v4u a, v4u b, v4f c) {
 
 __device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
 
-// Upper-triangle tile of block b.  Blocks are dispatched round-robin over the
-// 8 XCDs; each XCD gets a contiguous run of the row-major triangle order so
-// that the tiles resident on one XCD share row panels in its L2.
+// Upper-triangle tile of block b.  Tiles are ordered in G x G groups of the
+// tile grid (the diagonal groups are triangular), row-major inside a group.
+// Blocks are dispatched round-robin over the 8 XCDs; each XCD gets a
+// contiguous run of that order, so the ~64 tiles resident on one XCD at a
+// time fall in one group and read about 2G row panels, which its L2 serves.
+constexpr int TILE_GROUP = 8;
+
 __device__ __forceinline__ void tile_of_block(int b, int nt, int &ti, int &tj, int &lin) {
   const int ntiles = nt * (nt + 1) / 2;
   const int xcd = b & 7, loc = b >> 3, q = ntiles >> 3, r = ntiles & 7;
   int L = xcd * q + (xcd < r ? xcd : r) + loc;
   lin = L;
-  int t = 0, len = nt;
-  while (L >= len) { L -= len; ++t; --len; }
-  ti = t;
-  tj = t + L;
+  const int ng = (nt + TILE_GROUP - 1) / TILE_GROUP;
+  for (int gr = 0; gr < ng; ++gr) {
+    const int r0 = gr * TILE_GROUP, r1 = min(nt, r0 + TILE_GROUP);
+    for (int gc = gr; gc < ng; ++gc) {
+      const int c0 = gc * TILE_GROUP, c1 = min(nt, c0 + TILE_GROUP);
+      for (int t = r0; t < r1; ++t) {
+        const int first = (gc == gr) ? t : c0;   // diagonal group: tj >= ti
+        const int len = c1 - first;
+        if (L < len) {
+          ti = t;
+          tj = first + L;
+          return;
+        }
+        L -= len;
+      }
+    }
+  }
+  ti = tj = 0;   // not reached for b < ntiles
 }
 
-// Two tiles per CU when the accumulators fit in 256 registers; the folded and
-// 3-plane variants need the full 512-entry register file (one tile per CU).
-template <int P, bool FOLD>
-constexpr int gemm_min_blocks() { return (FOLD || Enc<P>::NP == 3) ? 1 : 2; }
-
-template <int P, bool FOLD>
-__global__ __launch_bounds__(NTH, (gemm_min_blocks<P, FOLD>())) void k_gemm(GemmArgs g) {
+// FP64 / FP32 product kernel: one 128 x 128 upper-triangle tile per block of
+// 4 waves (2 x 2 grid of 64 x 64), MFMA 16x16x4, two blocks per CU.
+template <int P>
+__global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
   using E = Enc<P>;
   using T = typename E::T;
   constexpr int NP = E::NP, KIND = E::KIND;
   constexpr int ES = sizeof(T);
-  constexpr int KT = (ES == 2) ? 32 : 128 / ES;   // K per LDS stage
+  constexpr int KT = 128 / ES;                    // K per LDS stage
   constexpr int EPC = 16 / ES;                    // elements per 16-byte chunk
   constexpr int LDR = KT + EPC;                   // LDS row stride (one chunk of padding)
   constexpr int CPR = KT / EPC;                   // chunks per row per plane
@@ -130,15 +145,12 @@ __global__ __launch_bounds__(NTH, (gemm_min_blocks<P, FOLD>())) void k_gemm(Gemm
       }
   };
 
-  Acc acc0[4][4], acc1[4][4], tot[4][4];
+  static_assert(KIND <= 1, "16-bit encodings use k_gemm16");
+  Acc acc0[4][4];
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) {
-      acc0[bi][bj] = Acc{};
-      acc1[bi][bj] = Acc{};
-      tot[bi][bj] = Acc{};
-    }
+    for (int bj = 0; bj < 4; ++bj) acc0[bi][bj] = Acc{};
 
   const int nk = (int)(Mp / KT);
   gload(0);
@@ -146,45 +158,7 @@ __global__ __launch_bounds__(NTH, (gemm_min_blocks<P, FOLD>())) void k_gemm(Gemm
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     if (kt + 1 < nk) gload(kt + 1);
-    if constexpr (KIND >= 2) {
-      v4u bf[NP][4];
-#pragma unroll
-      for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int bj = 0; bj < 4; ++bj)
-          bf[p][bj] = *(const v4u *)(Bs + (p * TILE + wn * 64 + bj * 16 + l16) * LDR + lg * 8);
-#pragma unroll
-      for (int bi = 0; bi < 4; ++bi) {
-        v4u af[NP];
-#pragma unroll
-        for (int p = 0; p < NP; ++p)
-          af[p] = *(const v4u *)(As + (p * TILE + wm * 64 + bi * 16 + l16) * LDR + lg * 8);
-#pragma unroll
-        for (int bj = 0; bj < 4; ++bj) {
-          acc0[bi][bj] = mfma16<KIND>(af[0], bf[0][bj], acc0[bi][bj]);
-          if constexpr (NP >= 2) {
-            acc1[bi][bj] = mfma16<KIND>(af[0], bf[1][bj], acc1[bi][bj]);
-            acc1[bi][bj] = mfma16<KIND>(af[1], bf[0][bj], acc1[bi][bj]);
-          }
-          if constexpr (NP == 3) {
-            acc1[bi][bj] = mfma16<KIND>(af[1], bf[1][bj], acc1[bi][bj]);
-            acc1[bi][bj] = mfma16<KIND>(af[0], bf[2][bj], acc1[bi][bj]);
-            acc1[bi][bj] = mfma16<KIND>(af[2], bf[0][bj], acc1[bi][bj]);
-          }
-        }
-      }
-      if constexpr (FOLD) {
-        if ((kt + 1) % g.fold == 0) {
-#pragma unroll
-          for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 4; ++bj) {
-              tot[bi][bj] += acc0[bi][bj];
-              acc0[bi][bj] = Acc{};
-            }
-        }
-      }
-    } else {
+    {
 #pragma unroll
       for (int ks = 0; ks < KT / 4; ++ks) {
         T bf[4];
@@ -232,9 +206,7 @@ __global__ __launch_bounds__(NTH, (gemm_min_blocks<P, FOLD>())) void k_gemm(Gemm
         const int64_t i = arow0 + wm * 64 + bi * 16 + acc_row<KIND>(lg, r);
         const int64_t j = brow0 + wn * 64 + bj * 16 + l16;
         if (diag_tile && i > j) continue;   // covered by the mirror of (j, i)
-        double v = (double)tot[bi][bj][r] + (double)acc0[bi][bj][r];
-        if constexpr (NP >= 2) v += (double)acc1[bi][bj][r];
-        v *= S;
+        const double v = (double)acc0[bi][bj][r] * S;
         T dp[NP], op[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p) dp[p] = Bg[p * PS + i * Mp + j];   // D(i, j)
@@ -347,6 +319,393 @@ __global__ __launch_bounds__(NTH, (gemm_min_blocks<P, FOLD>())) void k_gemm(Gemm
     }
   }
   if (tid == 0) g.tpart[lin] = ((tp[0] + tp[1]) + tp[2]) + tp[3];
+}
+
+// ------------------------------------------------ 16-bit product kernel
+// Pairs of horizontally adjacent 128 x 128 tiles, (ti, 2c) and (ti, 2c+1),
+// share one row panel of the left operand: a 128 x 256 output per block of
+// 4 waves, each wave 64 rows x 128 columns of one tile (4 x 8 MFMA blocks).
+// LDS is double-buffered (one barrier per K stage of 32).  All split
+// products of a K step go into one FP32 chunk accumulator, which is added
+// into a running FP32 total every `fold` K steps.  With r products per step
+// and n = K/32 steps the rounding error then grows like sqrt(r*fold + n/fold)
+// instead of sqrt(r*n): fold = sqrt(n/r) (the default) minimises it.  This
+// accumulation error, not the operand encoding, bounds the accuracy of the
+// split encodings at large M.
+constexpr int PAIR_COLS = 2;
+
+// Pair (ti, c) of block b, c >= ti/2, grouped like tile_of_block.
+__device__ __forceinline__ void pair_of_block(int b, int nt, int &ti, int &cp, int &lin) {
+  const int npc = nt / PAIR_COLS;
+  int npairs = 0;
+  for (int t = 0; t < nt; ++t) npairs += npc - t / PAIR_COLS;
+  const int xcd = b & 7, loc = b >> 3, q = npairs >> 3, r = npairs & 7;
+  int L = xcd * q + (xcd < r ? xcd : r) + loc;
+  lin = L;
+  const int ng = (nt + TILE_GROUP - 1) / TILE_GROUP;
+  constexpr int GP = TILE_GROUP / PAIR_COLS;
+  for (int gr = 0; gr < ng; ++gr) {
+    const int r0 = gr * TILE_GROUP, r1 = min(nt, r0 + TILE_GROUP);
+    for (int gc = gr; gc < ng; ++gc) {
+      const int c0 = gc * GP, c1 = min(npc, c0 + GP);
+      for (int t = r0; t < r1; ++t) {
+        const int first = max(c0, t / PAIR_COLS);
+        const int len = c1 - first;
+        if (len <= 0) continue;
+        if (L < len) {
+          ti = t;
+          cp = first + L;
+          return;
+        }
+        L -= len;
+      }
+    }
+  }
+  ti = cp = 0;
+}
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <int P>
+__global__ __launch_bounds__(NTH, 1) void k_gemm16(GemmArgs g) {
+  using E = Enc<P>;
+  using T = uint16_t;
+  constexpr int NP = E::NP, KIND = E::KIND;
+  constexpr int KT = 32;                         // K per stage: one MFMA step
+  constexpr int AR = TILE, BR = PAIR_COLS * TILE;
+  // A stage holds the A and B panel slices of every plane, rows of 64 bytes
+  // (4 chunks of 16 B) with the chunk order XOR-swizzled by (row / 4) % 4 so
+  // that the 16 rows read by one MFMA fragment hit distinct LDS banks.  Global
+  // data goes straight to LDS (global_load_lds, 16 B per lane: one wave
+  // instruction fills 16 contiguous rows).
+  constexpr int STAGE = NP * (AR + BR) * KT;     // halves per stage
+  // ring of NBUF stages, NBUF - 1 of them in flight while one is consumed
+  constexpr int NBUF_FIT = (150 * 1024) / (STAGE * 2);
+  constexpr int NBUF = NBUF_FIT > 4 ? 4 : (NBUF_FIT < 2 ? 2 : NBUF_FIT);
+  constexpr int PD = NBUF - 1;                   // prefetch distance (stages)
+  constexpr int BLK_A = NP * AR / 16, BLK_B = NP * BR / 16, BLK = BLK_A + BLK_B;
+  static_assert(BLK % 4 == 0, "whole blocks per wave");
+  constexpr int LPS = BLK / 4;                   // loads per stage per wave
+  // s_waitcnt immediate: vmcnt <= n, expcnt/lgkmcnt not waited on
+  constexpr int WAIT_STEADY = ((PD - 1) * LPS & 0xF) | ((((PD - 1) * LPS) >> 4) << 14) | (0x7 << 4) | (0xF << 8);
+  static_assert((PD - 1) * LPS <= 63, "vmcnt range");
+  constexpr int EPLD = TILE + 4;   // epilogue row pitch (floats)
+  constexpr int EPI = (2 * TILE * EPLD * 4 + (2 + 4) * TILE * 8 + 4 * 8) / 2;   // halves
+  constexpr int SMEM = NBUF * STAGE > EPI ? NBUF * STAGE : EPI;
+  __shared__ __attribute__((aligned(16))) T smem[SMEM];
+
+  int ti, cpair, lin;
+  pair_of_block(blockIdx.x, g.nt, ti, cpair, lin);
+  const int64_t Mp = g.Mp, PS = g.pstride;
+  const int64_t arow0 = (int64_t)ti * TILE, brow0 = (int64_t)cpair * BR;
+  const T *__restrict__ Ag = (const T *)g.A;
+  const T *__restrict__ Bg = (const T *)g.B;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = wave >> 1, rh = wave & 1, l16 = lane & 15, lg = lane >> 4;
+  const int tj = cpair * PAIR_COLS + h;
+  const bool valid = tj >= ti;
+
+  // per-lane source offsets of the wave's BLK/4 block loads (stage-invariant)
+  const int lrow = lane >> 2, lchunk = (lane & 3) ^ ((lane >> 4) & 3);
+  auto issue = [&](int kt, int buf) {
+    const int64_t k0 = (int64_t)kt * KT + lchunk * 8;
+    T *st = smem + buf * STAGE;
+#pragma unroll
+    for (int q = 0; q < BLK / 4; ++q) {
+      const int blk = wave + 4 * q;
+      const T *src;
+      T *dst;
+      if (blk < BLK_A) {
+        const int p = blk / (AR / 16), gq = blk % (AR / 16);
+        src = Ag + p * PS + (arow0 + gq * 16 + lrow) * Mp + k0;
+        dst = st + (p * AR + gq * 16) * KT;
+      } else {
+        const int bb = blk - BLK_A, p = bb / (BR / 16), gq = bb % (BR / 16);
+        src = Bg + p * PS + (brow0 + gq * 16 + lrow) * Mp + k0;
+        dst = st + NP * AR * KT + (p * BR + gq * 16) * KT;
+      }
+      __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)dst, 16, 0, 0);
+    }
+  };
+  // fragment: row (multiple of 16) + l16 of a plane, logical chunk lg
+  const int fslot = (lg ^ ((l16 >> 2) & 3)) * 8;
+
+  v4f acc[4][8], tot[4][8];
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 8; ++bj) {
+      acc[bi][bj] = v4f{};
+      tot[bi][bj] = v4f{};
+    }
+
+  // split products (plane of A, plane of B), largest first
+  constexpr int NPR = E::NPROD;
+  constexpr int PA[6] = {0, 0, 1, 1, 0, 2};
+  constexpr int PB[6] = {0, 1, 0, 1, 2, 0};
+
+  const int nk = (int)(Mp / KT);
+  const int fold = g.fold;   // >= 1 (resolved on the host)
+  // Waves of a tile below the diagonal run the same instruction stream (their
+  // results are discarded): the loop body stays branch-free, which keeps the
+  // accumulators in place across iterations.
+#pragma unroll
+  for (int s0 = 0; s0 < PD; ++s0)
+    if (s0 < nk) issue(s0, s0);
+  for (int k0 = 0; k0 < nk; k0 += fold) {
+    const int k1 = min(nk, k0 + fold);
+    for (int kt = k0; kt < k1; ++kt) {
+      // this wave's loads of stage kt have landed (later stages may still fly)
+      if (kt + PD - 1 < nk)
+        __builtin_amdgcn_s_waitcnt(WAIT_STEADY);
+      else
+        __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();   // ... and everyone's; the buffer of stage kt-1 is free
+      if (kt + PD < nk) issue(kt + PD, (kt + PD) % NBUF);
+      const T *As = smem + (kt % NBUF) * STAGE, *Bs = As + NP * AR * KT;
+      v4u af[4][NP];
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+          af[bi][p] = *(const v4u *)(As + (p * AR + rh * 64 + bi * 16 + l16) * KT + fslot);
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        v4u bf[4][NP];
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+          for (int p = 0; p < NP; ++p)
+            bf[bj][p] = *(const v4u *)(Bs + (p * BR + h * TILE + (half * 4 + bj) * 16 + l16) * KT +
+                                       fslot);
+#pragma unroll
+        for (int pr = 0; pr < NPR; ++pr)
+#pragma unroll
+          for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 4; ++bj)
+              acc[bi][half * 4 + bj] =
+                  mfma16<KIND>(af[bi][PA[pr]], bf[bj][PB[pr]], acc[bi][half * 4 + bj]);
+      }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 8; ++bj) {
+        tot[bi][bj] += acc[bi][bj];
+        acc[bi][bj] = v4f{};
+      }
+  }
+  __syncthreads();   // all waves done with the stage buffers (reused below)
+
+  // ------------------------------------------------------------ epilogue
+  // Phase 0: every wave dumps its FP32 results (total + chunk) into LDS,
+  // V[tile][row][col] with a row pitch of 132 floats.
+  float *V = (float *)smem;
+  double *rp = (double *)(V + 2 * TILE * EPLD);   // [2 tiles][128] row sums
+  double *cpart = rp + 2 * TILE;                  // [2 tiles][2 waves][128] column sums
+  double *tp = cpart + 4 * TILE;                  // [2 tiles][2 waves] tile sums
+  if (valid) {
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 8; ++bj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          V[(h * TILE + rh * 64 + bi * 16 + lg * 4 + r) * EPLD + bj * 16 + l16] = tot[bi][bj][r];
+  }
+  __syncthreads();
+  // Phase 1: 128 threads per tile, each owning two 8 x 8 blocks (block row
+  // br, block columns bc and bc + 8).  Row-contiguous 16-byte loads of D (and
+  // X2) and stores of the result; the mirrored store writes the transposed
+  // 8 x 8 block, again as 16-byte rows.
+  const int th = tid >> 7, x = tid & 127;
+  const int tjj = cpair * PAIR_COLS + th;
+  const bool tvalid = tjj >= ti, dtile = tjj == ti;
+  const int br = x >> 3;
+  const int64_t i0 = arow0 + br * 8;
+  const double S = E::PROD_SCALE;
+  T *__restrict__ Og = (T *)g.out;
+  double a_coef = 0.0, b_coef = 0.0;
+  if (g.mode == 1) {
+    const double c = g.coef[0];
+    a_coef = 1.0 - 2.0 * c;
+    b_coef = 2.0 + 2.0 * c;
+  }
+  double rsum[8], csum0[8], csum1[8], tsum = 0.0;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) rsum[r] = csum0[r] = csum1[r] = 0.0;
+  auto do_block = [&](const int bc, double (&csum)[8]) __attribute__((always_inline)) {
+    if (!tvalid || (dtile && br > bc)) return;   // below the diagonal: mirror of another block
+    const bool dblk = dtile && br == bc;
+    const int64_t j0 = (int64_t)tjj * TILE + bc * 8;
+    v4u ob[NP][8];   // encoded results, row r, 8 halves
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int64_t i = i0 + r;
+      v4u dv[NP], xv[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        dv[p] = *(const v4u *)(Bg + p * PS + i * Mp + j0);
+        if (g.mode == 1) xv[p] = *(const v4u *)(Ag + p * PS + i * Mp + j0);
+      }
+      const float *vr = V + (th * TILE + br * 8 + r) * EPLD + bc * 8;
+      uint16_t o[NP][8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t j = j0 + e;
+        T dp[NP], op[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) dp[p] = (uint16_t)(dv[p][e >> 1] >> (16 * (e & 1)));
+        const double v = (double)vr[e] * S;
+        double prod, diff;
+        if (g.mode == 0) {
+          double Dm, x2;
+          if (i == j) {
+            Dm = g.dg[i];
+            x2 = g.d2[i];
+          } else {
+            Dm = E::dec(dp);
+            x2 = v + Dm * (g.rD[i] + g.rD[j]);
+          }
+          E::enc(x2, op);
+          const double x2m = (i == j) ? x2 : E::dec(op);
+          if (i == j) g.s2[i] = x2 - E::dec(op);
+          prod = x2m * Dm;
+          diff = x2m - Dm;
+        } else {
+          double Dm, dn;
+          if (i == j) {
+            Dm = g.dg[i];
+            dn = a_coef * Dm + b_coef * g.d2[i] - 2.0 * g.d3[i];
+          } else {
+            T xp[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) xp[p] = (uint16_t)(xv[p][e >> 1] >> (16 * (e & 1)));
+            Dm = E::dec(dp);
+            const double X2m = E::dec(xp);
+            const double x3 = v + X2m * g.rD[j] + g.s2[i] * Dm;
+            dn = a_coef * Dm + b_coef * X2m - 2.0 * x3;
+          }
+          E::enc(dn, op);
+          const double dnm = (i == j) ? dn : E::dec(op);
+          if (i == j) {
+            g.dg_new[i] = dn;
+            g.rD_new[i] = dn - E::dec(op);
+          }
+          prod = dnm * dnm;
+          diff = dnm - Dm;
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) o[p][e] = op[p];
+        if (dblk && i > j) continue;   // lower half of a diagonal block
+        rsum[r] += prod;
+        if (i != j) {
+          csum[e] += prod;
+          tsum += 2.0 * diff * diff;
+        } else {
+          tsum += diff * diff;
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        v4u w;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = (uint32_t)o[p][2 * q] | ((uint32_t)o[p][2 * q + 1] << 16);
+        ob[p][r] = w;
+        if (!dblk) {
+          *(v4u *)(Og + p * PS + i * Mp + j0) = w;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (e >= r) Og[p * PS + i * Mp + j0 + e] = o[p][e];
+        }
+      }
+    }
+    // mirrored (transposed) block: row j0+e gets column e of the block
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        if (!dblk) {
+          v4u w;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const uint32_t lo = (ob[p][2 * q][e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+            const uint32_t hi = (ob[p][2 * q + 1][e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+            w[q] = lo | (hi << 16);
+          }
+          *(v4u *)(Og + p * PS + (j0 + e) * Mp + i0) = w;
+        } else {
+#pragma unroll
+          for (int r = 0; r < 8; ++r)
+            if (r < e)
+              Og[p * PS + (j0 + e) * Mp + i0 + r] =
+                  (uint16_t)((ob[p][r][e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+        }
+      }
+  };
+  do_block(x & 7, csum0);
+  do_block((x & 7) + 8, csum1);
+  // row sums: the 8 threads of a block row (lanes differing in bits 0..2)
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    double v = rsum[r];
+    v += shfl_xor_d(v, 1);
+    v += shfl_xor_d(v, 2);
+    v += shfl_xor_d(v, 4);
+    rsum[r] = v;
+  }
+  // column sums: the 8 block rows of a wave (bits 3..5), then the two waves
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    double v = csum0[e], w = csum1[e];
+    v += shfl_xor_d(v, 8);
+    v += shfl_xor_d(v, 16);
+    v += shfl_xor_d(v, 32);
+    w += shfl_xor_d(w, 8);
+    w += shfl_xor_d(w, 16);
+    w += shfl_xor_d(w, 32);
+    csum0[e] = v;
+    csum1[e] = w;
+  }
+  tsum += shfl_xor_d(tsum, 1);
+  tsum += shfl_xor_d(tsum, 2);
+  tsum += shfl_xor_d(tsum, 4);
+  tsum += shfl_xor_d(tsum, 8);
+  tsum += shfl_xor_d(tsum, 16);
+  tsum += shfl_xor_d(tsum, 32);
+  const int wt = (x >> 6);   // wave within the tile
+  if ((x & 7) == 0) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) rp[th * TILE + br * 8 + r] = rsum[r];
+  }
+  if ((lane >> 3) == 0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      cpart[(th * 2 + wt) * TILE + (x & 7) * 8 + e] = csum0[e];
+      cpart[(th * 2 + wt) * TILE + ((x & 7) + 8) * 8 + e] = csum1[e];
+    }
+  }
+  if (lane == 0) tp[th * 2 + wt] = tsum;
+  __syncthreads();
+  if (tvalid) {
+    const double rs = rp[th * TILE + x];
+    const double cs = cpart[(th * 2) * TILE + x] + cpart[(th * 2 + 1) * TILE + x];
+    if (!dtile) {
+      g.part[(int64_t)tjj * Mp + arow0 + x] = rs;
+      g.part[(int64_t)ti * Mp + (int64_t)tjj * TILE + x] = cs;
+    } else {
+      g.part[(int64_t)ti * Mp + arow0 + x] = rs + cs;
+    }
+  }
+  if (tid < 2) g.tpart[2 * lin + tid] = tp[tid * 2] + tp[tid * 2 + 1];   // 0 for a skipped tile
+}
+
+int pair_count(int nt) {
+  int n = 0;
+  for (int t = 0; t < nt; ++t) n += nt / PAIR_COLS - t / PAIR_COLS;
+  return n;
 }
 
 // ------------------------------------------------------------------ H stats
@@ -580,10 +939,10 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a) {
 // ---------------------------------------------------------------- dispatch
 template <int P>
 static hipError_t launch_gemm_p(const GemmArgs &g, int ntiles, hipStream_t st) {
-  if (g.fold > 0 && Enc<P>::KIND >= 2 && Enc<P>::NP >= 2)
-    k_gemm<P, true><<<ntiles, NTH, 0, st>>>(g);
+  if constexpr (Enc<P>::KIND >= 2)
+    k_gemm16<P><<<pair_count(g.nt), NTH, 0, st>>>(g);
   else
-    k_gemm<P, false><<<ntiles, NTH, 0, st>>>(g);
+    k_gemm<P><<<ntiles, NTH, 0, st>>>(g);
   return hipGetLastError();
 }
 

@@ -135,17 +135,18 @@ def test_precisions_trace_exact_and_error_bounded(precision):
         assert abs(res.iters - s["iters"]) <= (0 if precision == "fp64" else 1)
 
 
-@pytest.mark.parametrize("precision", ["fp16x3", "bf16x3"])
-def test_fold_accumulation_matches_unfolded(precision):
-    """Folding the FP32 accumulator changes only rounding."""
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x6"])
+@pytest.mark.parametrize("fold", [1, 3, 1000])
+def test_fold_period_changes_only_rounding(precision, fold):
+    """Any fold period (1 = every step, 1000 = never at this size) gives the
+    same result to the encoding's accuracy, with the trace exact."""
     w = workloads.spectral(512, 200, gap=0.1, seed=5)
     ref = oracle.projector_from_spectrum(w.Q, w.lam, w.N)
-    D0, r0 = run_gpu(w, precision, tol_ddbar=TOL_DDBAR[precision])
-    D1, r1 = run_gpu(w, precision, tol_ddbar=TOL_DDBAR[precision], fold_every=8)
-    assert r0.status == r1.status == gcp.OK
-    e0, e1 = rel_err(D0, ref), rel_err(D1, ref)
-    log(f"  {precision}: unfolded {e0:.3e} folded {e1:.3e}")
-    assert e1 < ERR_TOL[precision] and abs(np.trace(D1) - w.N) < 1e-10
+    D, r = run_gpu(w, precision, tol_ddbar=TOL_DDBAR[precision], fold_every=fold)
+    assert r.status == gcp.OK
+    e = rel_err(D, ref)
+    log(f"  {precision} fold={fold}: err {e:.3e}")
+    assert e < 2 * ERR_TOL[precision] and abs(np.trace(D) - w.N) < 1e-10
 
 
 def test_determinism_bitwise():
