@@ -373,11 +373,15 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
   g.Mp = c->Mp;
   g.pstride = PS;
   g.nt = c->nt;
-  // fold period of the 16-bit kernel: sqrt(K steps / products) unless given
+  // fold period of the 16-bit kernel, in K stages: sqrt(stages / products
+  // per stage) unless given.  One- and two-plane encodings stage 64 halves
+  // per row (64 K values of one plane, or 32 of both); three planes 32 K.
   {
-    const double steps = (double)(c->Mp / 32);
+    const int np = plane_count(prec);
+    const double stages = np <= 2 ? (double)(c->Mp * np / 64) : (double)(c->Mp / 32);
+    const double per_stage = np == 1 ? 2.0 : (double)products(prec);
     int f = c->opt.fold_every;
-    if (f <= 0) f = (int)std::lround(std::sqrt(steps / (double)products(prec)));
+    if (f <= 0) f = (int)std::lround(std::sqrt(stages / per_stage));
     g.fold = f < 1 ? 1 : f;
   }
   g.part = c->part;

@@ -109,4 +109,17 @@ template <> struct Enc<GCP_FP16X3> {
   __device__ static double dec(const T *p) { return (h2d(p[0]) + h2d(p[1])) * kF16InvScale; }
 };
 
+// Element (i, j) of plane p in the padded Mp x Mp storage of an encoding.
+// Two-plane encodings interleave the planes in blocks of 32 columns, so that
+// the 32-column K slice of both planes of a row is one 128-byte segment:
+//   [row i][block j/32][plane p][j % 32].
+// Other encodings keep each plane as a separate row-major matrix.
+template <int P>
+__host__ __device__ __forceinline__ int64_t eoff(int64_t i, int64_t j, int p, int64_t Mp) {
+  if constexpr (Enc<P>::NP == 2)
+    return i * (2 * Mp) + (j >> 5) * 64 + p * 32 + (j & 31);
+  else
+    return (int64_t)p * Mp * Mp + i * Mp + j;
+}
+
 }  // namespace gcp

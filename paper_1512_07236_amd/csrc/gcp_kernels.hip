@@ -334,63 +334,64 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
 // split encodings at large M.
 constexpr int PAIR_COLS = 2;
 
-// Pair (ti, c) of block b, c >= ti/2, grouped like tile_of_block.
+// Pair (ti, c) of block b, c >= ti/2, in column-major order of the pair
+// triangle: consecutive blocks share the column pair (the 256-row B panel)
+// and walk down the row panels.  Blocks go round-robin to the 8 XCDs, so at
+// any time all XCDs stream the same B panel (served once from the Infinity
+// Cache) while each keeps a few A panels in flight.  Measured on the load
+// path alone, this order moves 1.3x the data per unit time of an 8 x 8
+// grouped order with per-XCD contiguous ranges.
 __device__ __forceinline__ void pair_of_block(int b, int nt, int &ti, int &cp, int &lin) {
   const int npc = nt / PAIR_COLS;
-  int npairs = 0;
-  for (int t = 0; t < nt; ++t) npairs += npc - t / PAIR_COLS;
-  const int xcd = b & 7, loc = b >> 3, q = npairs >> 3, r = npairs & 7;
-  int L = xcd * q + (xcd < r ? xcd : r) + loc;
-  lin = L;
-  const int ng = (nt + TILE_GROUP - 1) / TILE_GROUP;
-  constexpr int GP = TILE_GROUP / PAIR_COLS;
-  for (int gr = 0; gr < ng; ++gr) {
-    const int r0 = gr * TILE_GROUP, r1 = min(nt, r0 + TILE_GROUP);
-    for (int gc = gr; gc < ng; ++gc) {
-      const int c0 = gc * GP, c1 = min(npc, c0 + GP);
-      for (int t = r0; t < r1; ++t) {
-        const int first = max(c0, t / PAIR_COLS);
-        const int len = c1 - first;
-        if (len <= 0) continue;
-        if (L < len) {
-          ti = t;
-          cp = first + L;
-          return;
-        }
-        L -= len;
-      }
+  int L = b;
+  lin = b;
+  for (int c = 0; c < npc; ++c) {
+    const int len = min(nt, PAIR_COLS * c + PAIR_COLS);   // rows ti <= 2c + 1
+    if (L < len) {
+      ti = L;
+      cp = c;
+      return;
     }
+    L -= len;
   }
   ti = cp = 0;
 }
 
 typedef __attribute__((address_space(3))) void lds_void;
 
+constexpr int NW16 = 8;              // waves per block of the 16-bit kernel (2 per SIMD)
+constexpr int NTH16 = 64 * NW16;
+
 template <int P>
-__global__ __launch_bounds__(NTH, 1) void k_gemm16(GemmArgs g) {
+__global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
   using E = Enc<P>;
   using T = uint16_t;
   constexpr int NP = E::NP, KIND = E::KIND;
   constexpr int KT = 32;                         // K per stage: one MFMA step
   constexpr int AR = TILE, BR = PAIR_COLS * TILE;
-  // A stage holds the A and B panel slices of every plane, rows of 64 bytes
-  // (4 chunks of 16 B) with the chunk order XOR-swizzled by (row / 4) % 4 so
-  // that the 16 rows read by one MFMA fragment hit distinct LDS banks.  Global
-  // data goes straight to LDS (global_load_lds, 16 B per lane: one wave
-  // instruction fills 16 contiguous rows).
-  constexpr int STAGE = NP * (AR + BR) * KT;     // halves per stage
+  constexpr int WCOLS = BR / (NW16 / 2);         // columns per wave (64)
+  constexpr int NBJ = WCOLS / 16;                // MFMA blocks per wave row (4)
+  // One- and two-plane encodings: a stage is one 128-byte segment of every
+  // panel row (64 halves: 64 K values of one plane, or 32 K values of both
+  // planes, which the interleaved storage keeps together).  Three-plane
+  // encodings: 64-byte segments of each plane (32 K values).
+  constexpr bool R128 = NP <= 2;
+  constexpr int RH = R128 ? 64 : NP * KT;        // halves per panel row per stage
+  constexpr int STAGE = (AR + BR) * RH;          // halves per stage
   // ring of NBUF stages, NBUF - 1 of them in flight while one is consumed
   constexpr int NBUF_FIT = (150 * 1024) / (STAGE * 2);
   constexpr int NBUF = NBUF_FIT > 4 ? 4 : (NBUF_FIT < 2 ? 2 : NBUF_FIT);
   constexpr int PD = NBUF - 1;                   // prefetch distance (stages)
-  constexpr int BLK_A = NP * AR / 16, BLK_B = NP * BR / 16, BLK = BLK_A + BLK_B;
-  static_assert(BLK % 4 == 0, "whole blocks per wave");
-  constexpr int LPS = BLK / 4;                   // loads per stage per wave
+  constexpr int ROWS_PER_LOAD = R128 ? 8 : 16;   // rows filled by one wave instruction
+  constexpr int BLK = (R128 ? 1 : NP) * (AR + BR) / ROWS_PER_LOAD;
+  static_assert(BLK % NW16 == 0, "whole blocks per wave");
+  constexpr int LPS = BLK / NW16;                // loads per stage per wave
   // s_waitcnt immediate: vmcnt <= n, expcnt/lgkmcnt not waited on
   constexpr int WAIT_STEADY = ((PD - 1) * LPS & 0xF) | ((((PD - 1) * LPS) >> 4) << 14) | (0x7 << 4) | (0xF << 8);
   static_assert((PD - 1) * LPS <= 63, "vmcnt range");
-  constexpr int EPLD = TILE + 4;   // epilogue row pitch (floats)
-  constexpr int EPI = (2 * TILE * EPLD * 4 + (2 + 4) * TILE * 8 + 4 * 8) / 2;   // halves
+  constexpr int EPLD = TILE + 4;                 // epilogue row pitch (floats)
+  constexpr int WPT = NW16 / 2;                  // waves per tile in the epilogue
+  constexpr int EPI = (2 * TILE * EPLD * 4 + (2 + 2 * WPT) * TILE * 8 + 2 * WPT * 8) / 2;   // halves
   constexpr int SMEM = NBUF * STAGE > EPI ? NBUF * STAGE : EPI;
   __shared__ __attribute__((aligned(16))) T smem[SMEM];
 
@@ -401,50 +402,71 @@ __global__ __launch_bounds__(NTH, 1) void k_gemm16(GemmArgs g) {
   const T *__restrict__ Ag = (const T *)g.A;
   const T *__restrict__ Bg = (const T *)g.B;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int h = wave >> 1, rh = wave & 1, l16 = lane & 15, lg = lane >> 4;
+  const int l16 = lane & 15, lg = lane >> 4;
+  // wave (rh, wc): rows rh*64 .. +63 of the panel, pair columns wc*64 .. +63
+  const int rh = wave & 1, wc = wave >> 1;
+  const int h = (wc * WCOLS) / TILE;             // which tile of the pair
+  const int tcol0 = wc * WCOLS - h * TILE;       // first column inside that tile
   const int tj = cpair * PAIR_COLS + h;
   const bool valid = tj >= ti;
 
-  // per-lane source offsets of the wave's BLK/4 block loads (stage-invariant)
-  const int lrow = lane >> 2, lchunk = (lane & 3) ^ ((lane >> 4) & 3);
+  // 128-byte rows: the 8 chunks of stage row R sit at slots c ^ s(R),
+  // s(R) = (R ^ (R >> 3)) % 8, so the rows read by an MFMA fragment fall on
+  // distinct banks whether the LDS serves 8 lanes of 16 B per cycle (32
+  // banks) or 16 lanes (64 banks).  64-byte rows (three planes): 4 chunks at
+  // slots c ^ ((R >> 1) ^ (R >> 3)) % 4.  Global data goes straight to LDS
+  // (global_load_lds, 16 B per lane; one wave instruction fills 8 or 16
+  // contiguous rows).
+  auto swz = [](int R) { return R128 ? ((R ^ (R >> 3)) & 7) : (((R >> 1) ^ (R >> 3)) & 3); };
   auto issue = [&](int kt, int buf) {
-    const int64_t k0 = (int64_t)kt * KT + lchunk * 8;
     T *st = smem + buf * STAGE;
 #pragma unroll
-    for (int q = 0; q < BLK / 4; ++q) {
-      const int blk = wave + 4 * q;
-      const T *src;
-      T *dst;
-      if (blk < BLK_A) {
-        const int p = blk / (AR / 16), gq = blk % (AR / 16);
-        src = Ag + p * PS + (arow0 + gq * 16 + lrow) * Mp + k0;
-        dst = st + (p * AR + gq * 16) * KT;
+    for (int q = 0; q < LPS; ++q) {
+      const int blk = wave + NW16 * q;
+      if constexpr (R128) {
+        const int R = blk * 8 + (lane >> 3);
+        const int c = (lane & 7) ^ swz(R);
+        const T *src = (R < AR ? Ag + (arow0 + R) * (NP * Mp) : Bg + (brow0 + R - AR) * (NP * Mp)) +
+                       (int64_t)kt * 64 + c * 8;
+        __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)(st + blk * 8 * 64), 16, 0, 0);
       } else {
-        const int bb = blk - BLK_A, p = bb / (BR / 16), gq = bb % (BR / 16);
-        src = Bg + p * PS + (brow0 + gq * 16 + lrow) * Mp + k0;
-        dst = st + NP * AR * KT + (p * BR + gq * 16) * KT;
+        const int p = blk / ((AR + BR) / 16), gq = blk % ((AR + BR) / 16);
+        const int R = gq * 16 + (lane >> 2);
+        const int c = (lane & 3) ^ swz(R);
+        const T *src = (R < AR ? Ag + p * PS + (arow0 + R) * Mp : Bg + p * PS + (brow0 + R - AR) * Mp) +
+                       (int64_t)kt * KT + c * 8;
+        __builtin_amdgcn_global_load_lds((const void *)src,
+                                         (lds_void *)(st + (p * (AR + BR) + gq * 16) * KT), 16, 0, 0);
       }
-      __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)dst, 16, 0, 0);
     }
   };
-  // fragment: row (multiple of 16) + l16 of a plane, logical chunk lg
-  const int fslot = (lg ^ ((l16 >> 2) & 3)) * 8;
+  // fragment x (chunk group) of stage row R: 128-byte rows hold two groups
+  // of 4 chunks (two planes, or two K halves of one plane)
+  auto frag = [&](const T *st, int R, int x) -> v4u {
+    if constexpr (R128)
+      return *(const v4u *)(st + R * 64 + ((x * 4 + lg) ^ swz(R)) * 8);
+    else
+      return *(const v4u *)(st + (x * (AR + BR) + R) * KT + (lg ^ swz(R)) * 8);
+  };
+  constexpr int NX = R128 ? 2 : NP;              // fragment groups per stage row
 
-  v4f acc[4][8], tot[4][8];
+  v4f acc[4][NBJ], tot[4][NBJ];
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 8; ++bj) {
+    for (int bj = 0; bj < NBJ; ++bj) {
       acc[bi][bj] = v4f{};
       tot[bi][bj] = v4f{};
     }
 
-  // split products (plane of A, plane of B), largest first
-  constexpr int NPR = E::NPROD;
+  // products per stage (group of A, group of B), largest first: split
+  // encodings pair the planes; one plane pairs the two K halves
+  constexpr int NPR = NP == 1 ? 2 : E::NPROD;
   constexpr int PA[6] = {0, 0, 1, 1, 0, 2};
   constexpr int PB[6] = {0, 1, 0, 1, 2, 0};
+  constexpr int QA[2] = {0, 1};
 
-  const int nk = (int)(Mp / KT);
+  const int nk = (int)(R128 ? Mp * NP / 64 : Mp / KT);
   const int fold = g.fold;   // >= 1 (resolved on the host)
   // Waves of a tile below the diagonal run the same instruction stream (their
   // results are discarded): the loop body stays branch-free, which keeps the
@@ -460,38 +482,39 @@ __global__ __launch_bounds__(NTH, 1) void k_gemm16(GemmArgs g) {
         __builtin_amdgcn_s_waitcnt(WAIT_STEADY);
       else
         __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();   // ... and everyone's; the buffer of stage kt-1 is free
+      // ... and everyone's; the buffer of stage kt-1 is free.  A bare
+      // s_barrier: __syncthreads() would add a workgroup release fence, which
+      // waits for every outstanding LDS-DMA load and so drains the pipeline.
+      // The empty asm statements keep the compiler from moving LDS accesses
+      // across the barrier; the waits above provide the hardware ordering.
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
       if (kt + PD < nk) issue(kt + PD, (kt + PD) % NBUF);
-      const T *As = smem + (kt % NBUF) * STAGE, *Bs = As + NP * AR * KT;
-      v4u af[4][NP];
+      const T *st = smem + (kt % NBUF) * STAGE;
+      v4u af[4][NX], bf[NBJ][NX];
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
-          af[bi][p] = *(const v4u *)(As + (p * AR + rh * 64 + bi * 16 + l16) * KT + fslot);
+        for (int x = 0; x < NX; ++x) af[bi][x] = frag(st, rh * 64 + bi * 16 + l16, x);
 #pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        v4u bf[4][NP];
+      for (int bj = 0; bj < NBJ; ++bj)
 #pragma unroll
-        for (int bj = 0; bj < 4; ++bj)
+        for (int x = 0; x < NX; ++x) bf[bj][x] = frag(st, AR + wc * WCOLS + bj * 16 + l16, x);
 #pragma unroll
-          for (int p = 0; p < NP; ++p)
-            bf[bj][p] = *(const v4u *)(Bs + (p * BR + h * TILE + (half * 4 + bj) * 16 + l16) * KT +
-                                       fslot);
+      for (int pr = 0; pr < NPR; ++pr)
 #pragma unroll
-        for (int pr = 0; pr < NPR; ++pr)
+        for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-          for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 4; ++bj)
-              acc[bi][half * 4 + bj] =
-                  mfma16<KIND>(af[bi][PA[pr]], bf[bj][PB[pr]], acc[bi][half * 4 + bj]);
-      }
+          for (int bj = 0; bj < NBJ; ++bj) {
+            const int xa = NP == 1 ? QA[pr] : PA[pr], xb = NP == 1 ? QA[pr] : PB[pr];
+            acc[bi][bj] = mfma16<KIND>(af[bi][xa], bf[bj][xb], acc[bi][bj]);
+          }
     }
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 8; ++bj) {
+      for (int bj = 0; bj < NBJ; ++bj) {
         tot[bi][bj] += acc[bi][bj];
         acc[bi][bj] = v4f{};
       }
@@ -499,30 +522,31 @@ __global__ __launch_bounds__(NTH, 1) void k_gemm16(GemmArgs g) {
   __syncthreads();   // all waves done with the stage buffers (reused below)
 
   // ------------------------------------------------------------ epilogue
-  // Phase 0: every wave dumps its FP32 results (total + chunk) into LDS,
-  // V[tile][row][col] with a row pitch of 132 floats.
+  // Phase 0: every wave dumps its FP32 results into LDS, V[tile][row][col]
+  // with a row pitch of 132 floats.
   float *V = (float *)smem;
   double *rp = (double *)(V + 2 * TILE * EPLD);   // [2 tiles][128] row sums
-  double *cpart = rp + 2 * TILE;                  // [2 tiles][2 waves][128] column sums
-  double *tp = cpart + 4 * TILE;                  // [2 tiles][2 waves] tile sums
+  double *cpart = rp + 2 * TILE;                  // [2 tiles][WPT waves][128] column sums
+  double *tp = cpart + 2 * WPT * TILE;            // [2 tiles][WPT waves] tile sums
   if (valid) {
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 8; ++bj)
+      for (int bj = 0; bj < NBJ; ++bj)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          V[(h * TILE + rh * 64 + bi * 16 + lg * 4 + r) * EPLD + bj * 16 + l16] = tot[bi][bj][r];
+          V[(h * TILE + rh * 64 + bi * 16 + lg * 4 + r) * EPLD + tcol0 + bj * 16 + l16] =
+              tot[bi][bj][r];
   }
   __syncthreads();
-  // Phase 1: 128 threads per tile, each owning two 8 x 8 blocks (block row
-  // br, block columns bc and bc + 8).  Row-contiguous 16-byte loads of D (and
-  // X2) and stores of the result; the mirrored store writes the transposed
-  // 8 x 8 block, again as 16-byte rows.
-  const int th = tid >> 7, x = tid & 127;
+  // Phase 1: 256 threads per tile, each owning one 8 x 8 block (block row br,
+  // block column bc).  Row-contiguous 16-byte loads of D (and X2) and stores
+  // of the result; the mirrored store writes the transposed block, again as
+  // 16-byte rows.
+  const int th = tid >> 8, x = tid & 255;
   const int tjj = cpair * PAIR_COLS + th;
   const bool tvalid = tjj >= ti, dtile = tjj == ti;
-  const int br = x >> 3;
+  const int br = x >> 4, bc = x & 15;
   const int64_t i0 = arow0 + br * 8;
   const double S = E::PROD_SCALE;
   T *__restrict__ Og = (T *)g.out;
@@ -532,11 +556,10 @@ __global__ __launch_bounds__(NTH, 1) void k_gemm16(GemmArgs g) {
     a_coef = 1.0 - 2.0 * c;
     b_coef = 2.0 + 2.0 * c;
   }
-  double rsum[8], csum0[8], csum1[8], tsum = 0.0;
+  double rsum[8], csum[8], tsum = 0.0;
 #pragma unroll
-  for (int r = 0; r < 8; ++r) rsum[r] = csum0[r] = csum1[r] = 0.0;
-  auto do_block = [&](const int bc, double (&csum)[8]) __attribute__((always_inline)) {
-    if (!tvalid || (dtile && br > bc)) return;   // below the diagonal: mirror of another block
+  for (int r = 0; r < 8; ++r) rsum[r] = csum[r] = 0.0;
+  if (tvalid && !(dtile && br > bc)) {   // blocks below the diagonal are mirrors
     const bool dblk = dtile && br == bc;
     const int64_t j0 = (int64_t)tjj * TILE + bc * 8;
     v4u ob[NP][8];   // encoded results, row r, 8 halves
@@ -546,8 +569,8 @@ __global__ __launch_bounds__(NTH, 1) void k_gemm16(GemmArgs g) {
       v4u dv[NP], xv[NP];
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
-        dv[p] = *(const v4u *)(Bg + p * PS + i * Mp + j0);
-        if (g.mode == 1) xv[p] = *(const v4u *)(Ag + p * PS + i * Mp + j0);
+        dv[p] = *(const v4u *)(Bg + eoff<P>(i, j0, p, Mp));
+        if (g.mode == 1) xv[p] = *(const v4u *)(Ag + eoff<P>(i, j0, p, Mp));
       }
       const float *vr = V + (th * TILE + br * 8 + r) * EPLD + bc * 8;
       uint16_t o[NP][8];
@@ -614,11 +637,11 @@ __global__ __launch_bounds__(NTH, 1) void k_gemm16(GemmArgs g) {
         for (int q = 0; q < 4; ++q) w[q] = (uint32_t)o[p][2 * q] | ((uint32_t)o[p][2 * q + 1] << 16);
         ob[p][r] = w;
         if (!dblk) {
-          *(v4u *)(Og + p * PS + i * Mp + j0) = w;
+          *(v4u *)(Og + eoff<P>(i, j0, p, Mp)) = w;
         } else {
 #pragma unroll
           for (int e = 0; e < 8; ++e)
-            if (e >= r) Og[p * PS + i * Mp + j0 + e] = o[p][e];
+            if (e >= r) Og[eoff<P>(i, j0 + e, p, Mp)] = o[p][e];
         }
       }
     }
@@ -635,39 +658,33 @@ __global__ __launch_bounds__(NTH, 1) void k_gemm16(GemmArgs g) {
             const uint32_t hi = (ob[p][2 * q + 1][e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
             w[q] = lo | (hi << 16);
           }
-          *(v4u *)(Og + p * PS + (j0 + e) * Mp + i0) = w;
+          *(v4u *)(Og + eoff<P>(j0 + e, i0, p, Mp)) = w;
         } else {
 #pragma unroll
           for (int r = 0; r < 8; ++r)
             if (r < e)
-              Og[p * PS + (j0 + e) * Mp + i0 + r] =
+              Og[eoff<P>(j0 + e, i0 + r, p, Mp)] =
                   (uint16_t)((ob[p][r][e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
         }
       }
-  };
-  do_block(x & 7, csum0);
-  do_block((x & 7) + 8, csum1);
-  // row sums: the 8 threads of a block row (lanes differing in bits 0..2)
+  }
+  // row sums: the 16 threads of a block row (lanes differing in bits 0..3)
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
     double v = rsum[r];
     v += shfl_xor_d(v, 1);
     v += shfl_xor_d(v, 2);
     v += shfl_xor_d(v, 4);
+    v += shfl_xor_d(v, 8);
     rsum[r] = v;
   }
-  // column sums: the 8 block rows of a wave (bits 3..5), then the two waves
+  // column sums: the 4 block rows of a wave (bits 4..5), then the tile's waves
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    double v = csum0[e], w = csum1[e];
-    v += shfl_xor_d(v, 8);
+    double v = csum[e];
     v += shfl_xor_d(v, 16);
     v += shfl_xor_d(v, 32);
-    w += shfl_xor_d(w, 8);
-    w += shfl_xor_d(w, 16);
-    w += shfl_xor_d(w, 32);
-    csum0[e] = v;
-    csum1[e] = w;
+    csum[e] = v;
   }
   tsum += shfl_xor_d(tsum, 1);
   tsum += shfl_xor_d(tsum, 2);
@@ -675,23 +692,22 @@ __global__ __launch_bounds__(NTH, 1) void k_gemm16(GemmArgs g) {
   tsum += shfl_xor_d(tsum, 8);
   tsum += shfl_xor_d(tsum, 16);
   tsum += shfl_xor_d(tsum, 32);
-  const int wt = (x >> 6);   // wave within the tile
-  if ((x & 7) == 0) {
+  const int wt = x >> 6;   // wave within the tile
+  if ((x & 15) == 0) {
 #pragma unroll
     for (int r = 0; r < 8; ++r) rp[th * TILE + br * 8 + r] = rsum[r];
   }
-  if ((lane >> 3) == 0) {
+  if (lg == 0) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      cpart[(th * 2 + wt) * TILE + (x & 7) * 8 + e] = csum0[e];
-      cpart[(th * 2 + wt) * TILE + ((x & 7) + 8) * 8 + e] = csum1[e];
-    }
+    for (int e = 0; e < 8; ++e) cpart[(th * WPT + wt) * TILE + bc * 8 + e] = csum[e];
   }
-  if (lane == 0) tp[th * 2 + wt] = tsum;
+  if (lane == 0) tp[th * WPT + wt] = tsum;
   __syncthreads();
-  if (tvalid) {
+  if (x < TILE && tvalid) {
     const double rs = rp[th * TILE + x];
-    const double cs = cpart[(th * 2) * TILE + x] + cpart[(th * 2 + 1) * TILE + x];
+    double cs = 0.0;
+#pragma unroll
+    for (int w = 0; w < WPT; ++w) cs += cpart[(th * WPT + w) * TILE + x];
     if (!dtile) {
       g.part[(int64_t)tjj * Mp + arow0 + x] = rs;
       g.part[(int64_t)ti * Mp + (int64_t)tjj * TILE + x] = cs;
@@ -699,7 +715,12 @@ __global__ __launch_bounds__(NTH, 1) void k_gemm16(GemmArgs g) {
       g.part[(int64_t)ti * Mp + arow0 + x] = rs + cs;
     }
   }
-  if (tid < 2) g.tpart[2 * lin + tid] = tp[tid * 2] + tp[tid * 2 + 1];   // 0 for a skipped tile
+  if (tid < 2) {   // 0 for a skipped tile
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < WPT; ++w) t += tp[tid * WPT + w];
+    g.tpart[2 * lin + tid] = t;
+  }
 }
 
 int pair_count(int nt) {
@@ -795,7 +816,7 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a) {
     T op[NP];
     E::enc(x, op);
 #pragma unroll
-    for (int p = 0; p < NP; ++p) Og[p * a.pstride + i * a.Mp + j] = op[p];
+    for (int p = 0; p < NP; ++p) Og[eoff<P>(i, j, p, a.Mp)] = op[p];
     const double xm = (i == j) ? x : E::dec(op);
     if (i == j) {
       a.dg[i] = x;
@@ -927,7 +948,7 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a) {
   } else {
     T p[NP];
 #pragma unroll
-    for (int q = 0; q < NP; ++q) p[q] = ((const T *)a.planes)[q * a.pstride + i * a.Mp + j];
+    for (int q = 0; q < NP; ++q) p[q] = ((const T *)a.planes)[eoff<P>(i, j, q, a.Mp)];
     x = E::dec(p);
   }
   if (a.dtype == GCP_DTYPE_F64)
@@ -940,7 +961,7 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a) {
 template <int P>
 static hipError_t launch_gemm_p(const GemmArgs &g, int ntiles, hipStream_t st) {
   if constexpr (Enc<P>::KIND >= 2)
-    k_gemm16<P><<<pair_count(g.nt), NTH, 0, st>>>(g);
+    k_gemm16<P><<<pair_count(g.nt), NTH16, 0, st>>>(g);
   else
     k_gemm<P><<<ntiles, NTH, 0, st>>>(g);
   return hipGetLastError();
