@@ -84,6 +84,61 @@ def cpu_baseline(w, iters_per_solve: int, launches_per_solve: int, budget_s: flo
     }
 
 
+COPY_BYTES = 1 << 30
+
+
+def copy_calibration() -> None:
+    """A plain device-to-device copy of exactly COPY_BYTES (read COPY_BYTES,
+    write COPY_BYTES): the yardstick for the memory-traffic counters."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def _counter_rows(d: str):
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        rows += list(csv.DictReader(open(f)))
+    return rows
+
+
+def summarize_pmc(precision: str, scale: int, fetch_dir: str, write_dir: str) -> int:
+    """profiles/<kernel>_pmc.json from FETCH_SIZE / WRITE_SIZE runs (KiB per
+    dispatch), each scaled by what the same counter reads for the 1 GiB copy."""
+    import hashlib
+    import paper_1512_07236_amd as gcp
+    prec = gcp.Precision.parse(precision)
+    M = 8192 // scale
+    kname = "k_gemm16" if gcp.PRODUCTS[prec] > 1 or prec in (gcp.Precision.BF16, gcp.Precision.FP16) else "k_gemm"
+    tag = f"gemm_{prec.name.lower()}_M{M}"
+    out = {"kernel": f"{kname}<{int(prec)}>", "workload": f"M={M}", "precision": prec.name.lower()}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _counter_rows(d) if r["Counter_Name"] == name]
+        kern = [float(r["Counter_Value"]) for r in rows if f"{kname}<{int(prec)}>" in r["Kernel_Name"]]
+        copy = [float(r["Counter_Value"]) for r in rows
+                if ("copy" in r["Kernel_Name"].lower() or "elementwise" in r["Kernel_Name"].lower())
+                and float(r["Counter_Value"]) * 1024 > 0.5 * COPY_BYTES]
+        if not kern or not copy:
+            print(f"no {name} rows for the kernel or the copy in {d}", file=sys.stderr)
+            return 1
+        factor = (max(copy) * 1024) / COPY_BYTES   # counter bytes per true byte
+        out[name] = {"kib_per_launch_raw": sum(kern) / len(kern), "launches": len(kern),
+                     "copy_kib_raw": max(copy), "copy_factor": factor,
+                     "bytes_per_launch": sum(kern) / len(kern) * 1024 / factor}
+    out["hbm_bytes_per_launch"] = out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"]
+    src = open(os.path.join(ROOT, "paper_1512_07236_amd", "csrc", "gcp_kernels.hip"), "rb").read()
+    out["kernel_source_sha256"] = hashlib.sha256(src).hexdigest()
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    path = os.path.join(ROOT, "profiles", f"{tag}_pmc.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(path)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,7 +153,15 @@ def main() -> int:
     ap.add_argument("--scale", type=int, default=1, help="divide M by this (quick runs only)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (the reference kernel that scales "
+                         "rocprofv3 FETCH_SIZE/WRITE_SIZE to bytes)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "'bench.py --copy-calibration' into profiles/<kernel>_pmc.json and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        return summarize_pmc(args.precision, args.scale, *args.pmc_summary)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -180,6 +243,9 @@ def main() -> int:
                 / (g64 * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"]}
         log(f"[bench] FP64: {t64*1e3:.1f} ms/solve, iters={res64[-1].iters}, err={err64:.3e}")
 
+    if args.copy_calibration:
+        copy_calibration()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle sample")
@@ -211,7 +277,9 @@ def main() -> int:
         "speedup_vs_fp64": (fp64["time_to_solution_ms"] / (t_mixed * 1e3)) if fp64 else None,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": f"k_gemm<{prec.name}>", "launches_per_solve": launches,
+                     "kernel": (f"k_gemm16<{prec.name}>" if gcp.MFMA_DTYPE[prec] in ("fp16", "bf16")
+                                else f"k_gemm<{prec.name}>"),
+                     "launches_per_solve": launches,
                      "ms_per_launch": gemm_ms_avg,
                      "mfma_issued_tflops": mfma_achieved,
                      "mfma_issued_frac": mfma_achieved / peak},
