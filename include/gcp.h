@@ -87,6 +87,10 @@ typedef struct {
                             the accumulated rounding, the dominant error of the
                             split encodings at large M; a value >= K/32 never folds. */
     int32_t profile;     /* 1: time every matrix-product launch with HIP events */
+    int32_t keep_iterates; /* 1: gcp_purify keeps D_0 .. D_{p-1} for gcp_backward, one
+                              M x M matrix of the adjoint's type per update (default 0) */
+    int32_t bwd_precision; /* arithmetic of gcp_backward: GCP_FP64 (default) or GCP_FP32
+                              (FP32 MFMA and storage; kappa and the traces stay FP64) */
 } gcp_options;
 
 typedef struct {
@@ -135,6 +139,27 @@ int gcp_init(gcp_ctx *ctx, const double *H, int64_t ldh, int64_t N, double emin,
  * holds the last iterate and *out is filled in every case; out may be NULL).
  * Calling it again re-runs the solve from the D_0 of the last gcp_init. */
 int gcp_purify(gcp_ctx *ctx, void *D, int32_t dtype, int64_t ldd, gcp_result *out);
+
+/* Reverse mode of the last gcp_purify (which must have run with keep_iterates = 1,
+ * after the last gcp_init): given dL/dD of the returned matrix D_p (device,
+ * M x M, leading dimension ldg, dtype gcp_dtype; read as its symmetric part),
+ * writes dL/dH (device, M x M, leading dimension ldh, same dtype), the
+ * gradient with respect to symmetric perturbations of H, for the p updates
+ * that gcp_purify applied, whatever its status.
+ *   - Each update of eq. (hpcp3), D' = (1-2c) D + (2+2c) D^2 - 2 D^3 with
+ *     c = (T2 - T3)/(T1 - T2), is differentiated including the dependence of
+ *     c on D; this costs two symmetric and two general M x M products per
+ *     update (about three times the forward).
+ *   - The initial guess of eqs. (dmguess),(pmcpguess) is differentiated
+ *     through mu = Tr(H)/M and beta(mu), with emin/emax held fixed (also when
+ *     they were Gershgorin bounds derived from H).
+ *   - N = 0 or N = M gives dL/dH = 0 (D_0 does not depend on H).
+ * The stored iterates stay valid for repeated calls (several loss gradients).
+ * out may be NULL; out->iters = p, out->gemm_* count the adjoint products and
+ * out->ms_total is the host wall time.  Errors: STATE without a purify that
+ * kept its iterates, INVALID_ARG for NULL pointers, ld < M or a bad dtype. */
+int gcp_backward(gcp_ctx *ctx, const void *dL_dD, int64_t ldg, void *dL_dH, int64_t ldh,
+                 int32_t dtype, gcp_result *out);
 
 /* Per-iterate history of the last gcp_purify: GCP_HIST_COLS doubles per row,
  *   [n, Tr D, Tr D^2, Tr D^3, c_n, Omega = ||D^2-D||_F^2, gamma_n = (1-2c_n)/3,

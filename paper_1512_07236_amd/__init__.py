@@ -66,7 +66,8 @@ HIST_FIELDS = ("n", "t1", "t2", "t3", "c", "omega", "gamma", "lagrangian", "step
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("tol_ddbar", ctypes.c_double), ("tol_idem", ctypes.c_double),
-                ("fold_every", ctypes.c_int32), ("profile", ctypes.c_int32)]
+                ("fold_every", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("keep_iterates", ctypes.c_int32), ("bwd_precision", ctypes.c_int32)]
 
 
 class CResult(ctypes.Structure):
@@ -107,6 +108,8 @@ def load_library() -> ctypes.CDLL:
     L.gcp_init.restype = ctypes.c_int
     L.gcp_purify.argtypes = [vp, vp, i32, i64, ctypes.POINTER(CResult)]
     L.gcp_purify.restype = ctypes.c_int
+    L.gcp_backward.argtypes = [vp, vp, i64, vp, i64, i32, ctypes.POINTER(CResult)]
+    L.gcp_backward.restype = ctypes.c_int
     L.gcp_get_history.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32)]
     L.gcp_get_history.restype = ctypes.c_int
     L.gcp_get_init_scalars.argtypes = [vp] + [ctypes.POINTER(ctypes.c_double)] * 4
@@ -157,7 +160,8 @@ class Context:
     """A purification context for M x M problems (owns the device workspace)."""
 
     def __init__(self, M: int, precision="fp64", max_iter: int = 100, tol_ddbar: float = 1e-6,
-                 tol_idem: float = 0.0, fold_every: int = 0, profile: bool = False, stream=None):
+                 tol_idem: float = 0.0, fold_every: int = 0, profile: bool = False,
+                 keep_iterates: bool = False, bwd_precision="fp64", stream=None):
         L = load_library()
         self._L = L
         self.M = int(M)
@@ -169,6 +173,8 @@ class Context:
         o.tol_idem = float(tol_idem)
         o.fold_every = int(fold_every)
         o.profile = 1 if profile else 0
+        o.keep_iterates = 1 if keep_iterates else 0
+        o.bwd_precision = int(Precision.parse(bwd_precision))
         self.options = o
         self._stream = stream
         h = ctypes.c_void_p()
@@ -212,6 +218,27 @@ class Context:
         return out, Result(r.status, r.iters, r.t1, r.t2, r.c_last, r.idem, r.ms_total, r.gemm_ms,
                            r.gemm_launches, r.gemm_flops, r.mfma_flops, self.history())
 
+    def backward(self, dL_dD, out=None):
+        """dL/dH for the loss gradient dL_dD of the last purify's result
+        (needs keep_iterates=True).  Returns (dL_dH, Result)."""
+        import torch
+        if not (isinstance(dL_dD, torch.Tensor) and dL_dD.is_cuda and
+                dL_dD.dtype in (torch.float64, torch.float32) and dL_dD.stride(1) == 1 and
+                tuple(dL_dD.shape) == (self.M, self.M)):
+            raise ValueError("dL_dD must be an M x M float64/float32 CUDA tensor with unit "
+                             "column stride")
+        if out is None:
+            out = torch.empty((self.M, self.M), dtype=dL_dD.dtype, device=dL_dD.device)
+        if out.dtype != dL_dD.dtype or out.stride(1) != 1 or tuple(out.shape) != (self.M, self.M):
+            raise ValueError("out must match dL_dD's dtype and shape with unit column stride")
+        dt = DTYPE_F64 if out.dtype == torch.float64 else DTYPE_F32
+        r = CResult()
+        self._check(self._L.gcp_backward(self._h, ctypes.c_void_p(dL_dD.data_ptr()),
+                                         dL_dD.stride(0), ctypes.c_void_p(out.data_ptr()),
+                                         out.stride(0), dt, ctypes.byref(r)))
+        return out, Result(r.status, r.iters, r.t1, r.t2, r.c_last, r.idem, r.ms_total, r.gemm_ms,
+                           r.gemm_launches, r.gemm_flops, r.mfma_flops, np.zeros((0, HIST_COLS)))
+
     def history(self) -> np.ndarray:
         n = ctypes.c_int32()
         self._check(self._L.gcp_get_history(self._h, None, 0, ctypes.byref(n)))
@@ -251,3 +278,40 @@ def purify(H, N: int, emin: float = math.nan, emax: float = math.nan, precision=
     with Context(H.shape[0], precision=precision, **options) as ctx:
         ctx.init(H, N, emin, emax)
         return ctx.purify(out=out)
+
+
+def _autograd_function():
+    import torch
+
+    class _Purify(torch.autograd.Function):
+        """D = purify(H): forward and backward both run in libgcp."""
+
+        @staticmethod
+        def forward(ctx, H, N, emin, emax, options):
+            c = Context(H.shape[0], keep_iterates=True, **options)
+            c.init(H.detach().contiguous(), N, emin, emax)
+            D, res = c.purify(dtype=H.dtype, raise_on_failure=True)
+            ctx.gcp = c
+            ctx.result = res
+            return D
+
+        @staticmethod
+        def backward(ctx, gD):
+            dH, _ = ctx.gcp.backward(gD.contiguous())
+            ctx.gcp.close()
+            return dH, None, None, None, None
+
+    return _Purify
+
+
+_PURIFY_FN = None
+
+
+def purify_autograd(H, N: int, emin: float = math.nan, emax: float = math.nan, **options):
+    """Differentiable D(H): a torch.autograd.Function whose backward is the
+    library's adjoint (gcp_backward).  The context, with its stored iterates,
+    lives until the backward has run.  options are those of Context (FP64 H)."""
+    global _PURIFY_FN
+    if _PURIFY_FN is None:
+        _PURIFY_FN = _autograd_function()
+    return _PURIFY_FN.apply(H, int(N), float(emin), float(emax), dict(options))

@@ -77,6 +77,13 @@ struct gcp_ctx {
   double t1_0 = NAN, t2_0 = NAN;
   void *D0p = nullptr;      // copy of the D_0 planes so purify can be re-run
   double *dg0 = nullptr, *rD0 = nullptr, *d20 = nullptr;
+  // reverse mode: stored iterates D_0 .. D_{p-1} (adjoint type, Mp x Mp each)
+  std::vector<void *> slots;
+  int bwd_p = -1;           // updates covered by the stored iterates (-1: none)
+  void *bG[2] = {nullptr, nullptr};
+  void *bX2 = nullptr, *bAT = nullptr, *bCT = nullptr;
+  double *btpart = nullptr; // upper-tile partial sums
+  double *bvec = nullptr;   // 2 Mp row scratch + kappa + 2 sums
   // profiling
   std::vector<hipEvent_t> events;
   std::string err;
@@ -102,6 +109,12 @@ static void free_all(gcp_ctx *c) {
                   c->counter, c->sc, c->hist, c->D0p, c->dg0, c->rD0, c->d20};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  void *bptrs[] = {c->bG[0], c->bG[1], c->bX2, c->bAT, c->bCT, c->btpart, c->bvec};
+  for (void *p : bptrs)
+    if (p) (void)hipFree(p);
+  for (void *p : c->slots)
+    if (p) (void)hipFree(p);
+  c->slots.clear();
   if (c->sc_host) (void)hipHostFree(c->sc_host);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   c->events.clear();
@@ -116,6 +129,8 @@ extern "C" int gcp_options_default(gcp_options *opt) {
   opt->tol_idem = 0.0;
   opt->fold_every = 0;
   opt->profile = 0;
+  opt->keep_iterates = 0;
+  opt->bwd_precision = GCP_FP64;
   return GCP_OK;
 }
 
@@ -138,6 +153,11 @@ extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void
   if (o.max_iter < 0 || o.max_iter > 100000 || !(o.tol_ddbar >= 0.0) || !(o.tol_idem >= 0.0) ||
       o.fold_every < 0) {
     g_create_error = "gcp_create: max_iter, tolerances and fold_every must be non-negative";
+    return GCP_ERR_INVALID_ARG;
+  }
+  if ((o.keep_iterates != 0 && o.keep_iterates != 1) ||
+      (o.bwd_precision != GCP_FP64 && o.bwd_precision != GCP_FP32)) {
+    g_create_error = "gcp_create: keep_iterates must be 0 or 1 and bwd_precision FP64 or FP32";
     return GCP_ERR_INVALID_ARG;
   }
   gcp_ctx *c = new (std::nothrow) gcp_ctx();
@@ -190,6 +210,16 @@ extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void
   alloc((void **)&c->counter, sizeof(unsigned));
   alloc((void **)&c->sc, sizeof(Scalars));
   alloc((void **)&c->hist, (size_t)(o.max_iter + 1) * GCP_HIST_COLS * sizeof(double));
+  if (o.keep_iterates) {
+    const size_t bb = Mp * Mp * (size_t)elem_size(o.bwd_precision);
+    alloc(&c->bG[0], bb);
+    alloc(&c->bG[1], bb);
+    alloc(&c->bX2, bb);
+    alloc(&c->bAT, bb);
+    alloc(&c->bCT, bb);
+    alloc((void **)&c->btpart, (size_t)c->nt * (c->nt + 1) / 2 * sizeof(double));
+    alloc((void **)&c->bvec, (2 * Mp + 8) * sizeof(double));
+  }
   if (ok && hipHostMalloc((void **)&c->sc_host, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
     ok = false;
   if (!ok) {
@@ -249,6 +279,7 @@ extern "C" int gcp_init(gcp_ctx *c, const double *H, int64_t ldh, int64_t N, dou
                         double emax) {
   if (!c) return GCP_ERR_INVALID_ARG;
   c->inited = false;
+  c->bwd_p = -1;
   if (!H || ldh < c->M || N < 0 || N > c->M) {
     c->err = "gcp_init: need H != NULL, ldh >= M and 0 <= N <= M";
     return GCP_ERR_INVALID_ARG;
@@ -323,6 +354,22 @@ extern "C" int gcp_get_init_scalars(const gcp_ctx *c, double *mu, double *beta, 
   return GCP_OK;
 }
 
+// Keeps iterate D_n (forward planes Dp[k] plus its FP64 diagonal) as slot n.
+static int store_iterate(gcp_ctx *c, int n, int k) {
+  const size_t bytes = (size_t)c->Mp * (size_t)c->Mp * (size_t)elem_size(c->opt.bwd_precision);
+  while ((int)c->slots.size() <= n) {
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      c->err = "gcp_purify: out of device memory for the iterates kept for gcp_backward";
+      return GCP_ERR_NO_MEMORY;
+    }
+    c->slots.push_back(p);
+  }
+  HIPCHK(c, launch_bwd_store(c->opt.precision, c->opt.bwd_precision, c->Dp[k], c->dg[k], c->Mp,
+                             c->slots[n], c->stream));
+  return GCP_OK;
+}
+
 extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_result *res) {
   if (!c) return GCP_ERR_INVALID_ARG;
   if (!c->inited) {
@@ -350,6 +397,13 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
   s0.t2 = c->t2_0;
   *c->sc_host = s0;
   HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
+
+  const bool keep = c->opt.keep_iterates != 0;
+  c->bwd_p = -1;
+  if (keep) {
+    const int st = store_iterate(c, 0, 0);
+    if (st != GCP_OK) return st;
+  }
 
   const bool prof = c->opt.profile != 0;
   const int max_launch = 2 * max_iter + 2;
@@ -409,6 +463,10 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
     HIPCHK(c, hipStreamSynchronize(c->stream));
     status = c->sc_host->status;
     if (status != 0) break;
+    if (keep && n > 0) {
+      st = store_iterate(c, n, k);
+      if (st != GCP_OK) return st;
+    }
     // K2: D_{n+1} = (1 - 2c) D + (2 + 2c) X2 - 2 X2 D
     g.mode = 1;
     g.A = c->X2p;
@@ -423,6 +481,7 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
     c->cur = 1 - k;
   }
   const int iters = n;
+  if (keep) c->bwd_p = iters;
   // output D_p
   OutArgs oa{};
   oa.planes = c->Dp[c->cur];
@@ -472,6 +531,131 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
     c->err = status == 2 ? "gcp_purify: max_iter reached before the tolerance"
                          : "gcp_purify: breakdown (c outside [0,1], Tr(D Dbar) < 0 or non-finite)";
   return rc;
+}
+
+extern "C" int gcp_backward(gcp_ctx *c, const void *dLdD, int64_t ldg, void *dLdH, int64_t ldh,
+                            int32_t dtype, gcp_result *res) {
+  if (!c) return GCP_ERR_INVALID_ARG;
+  if (c->bwd_p < 0 || !c->inited) {
+    c->err = "gcp_backward: needs a gcp_purify with keep_iterates = 1 after the last gcp_init";
+    return GCP_ERR_STATE;
+  }
+  if (!dLdD || !dLdH || ldg < c->M || ldh < c->M ||
+      (dtype != GCP_DTYPE_F64 && dtype != GCP_DTYPE_F32)) {
+    c->err = "gcp_backward: need non-NULL buffers, ldg >= M, ldh >= M and dtype F64 or F32";
+    return GCP_ERR_INVALID_ARG;
+  }
+  const auto t_start = std::chrono::steady_clock::now();
+  const int bprec = c->opt.bwd_precision;
+  const int p = c->bwd_p;
+  const bool prof = c->opt.profile != 0;
+  const int nlaunch_max = 3 * p;
+  if (prof && (int)c->events.size() < 2 * nlaunch_max) {
+    for (int k = (int)c->events.size(); k < 2 * nlaunch_max; ++k) {
+      hipEvent_t e;
+      HIPCHK(c, hipEventCreate(&e));
+      c->events.push_back(e);
+    }
+  }
+  int nlaunch = 0;
+  double flops = 0.0, mflops = 0.0;
+  const double Md = (double)c->M, tile_fl = 2.0 * 128.0 * 128.0 * (double)c->Mp;
+  const int ntri = c->nt * (c->nt + 1) / 2;
+  auto gemm = [&](BwdArgs &a) -> int {
+    if (prof) HIPCHK(c, hipEventRecord(c->events[2 * nlaunch], c->stream));
+    HIPCHK(c, launch_bwd_gemm(bprec, a, c->stream));
+    if (prof) HIPCHK(c, hipEventRecord(c->events[2 * nlaunch + 1], c->stream));
+    ++nlaunch;
+    if (a.mode == 1) {
+      flops += 4.0 * Md * Md * Md;
+      mflops += 2.0 * c->nt * c->nt * tile_fl;
+    } else {
+      flops += Md * Md * (Md + 1.0);
+      mflops += ntri * tile_fl;
+    }
+    return GCP_OK;
+  };
+
+  HIPCHK(c, launch_bwd_load(bprec, dLdD, ldg, dtype, c->M, c->Mp, c->bG[0], c->stream));
+  int cur = 0;
+  double *kappa = c->bvec + 2 * c->Mp;
+  BwdArgs a{};
+  a.Mp = c->Mp;
+  a.nt = c->nt;
+  a.X2 = c->bX2;
+  a.AT = c->bAT;
+  a.CT = c->bCT;
+  a.kappa = kappa;
+  a.tpart = c->btpart;
+  for (int n = p - 1; n >= 0; --n) {
+    const double *h = c->hist_host.data() + (size_t)n * GCP_HIST_COLS;
+    const double cn = h[4], t12 = h[1] - h[2];
+    a.D = c->slots[n];
+    a.G = c->bG[cur];
+    a.a = 1.0 - 2.0 * cn;
+    a.b = 2.0 + 2.0 * cn;
+    a.c = cn;
+    a.inv_t12 = 1.0 / t12;
+    // X2 = D D and the partial sums of kappa
+    a.mode = 0;
+    a.out0 = c->bX2;
+    int st = gemm(a);
+    if (st != GCP_OK) return st;
+    HIPCHK(c, launch_bwd_kappa(c->btpart, ntri, kappa, c->stream));
+    // AT = D G, CT = X2 G
+    a.mode = 1;
+    a.out0 = c->bAT;
+    a.out1 = c->bCT;
+    st = gemm(a);
+    if (st != GCP_OK) return st;
+    // Gbar_n
+    a.mode = 2;
+    a.out0 = c->bG[1 - cur];
+    st = gemm(a);
+    if (st != GCP_OK) return st;
+    cur = 1 - cur;
+  }
+  BwdInitArgs ia{};
+  ia.G0 = c->bG[cur];
+  ia.D0 = c->slots[0];
+  ia.M = c->M;
+  ia.Mp = c->Mp;
+  ia.ldh = ldh;
+  ia.theta = (double)c->N / (double)c->M;
+  ia.beta = c->beta;
+  ia.dbeta = 0.0;
+  if (c->N > 0 && c->N < c->M) {
+    const double bt = ia.theta / (c->emax - c->mu), bb = (1.0 - ia.theta) / (c->mu - c->emin);
+    ia.dbeta = bt <= bb ? ia.theta / ((c->emax - c->mu) * (c->emax - c->mu))
+                        : -(1.0 - ia.theta) / ((c->mu - c->emin) * (c->mu - c->emin));
+  }
+  ia.rows = c->bvec;
+  ia.sums = c->bvec + 2 * c->Mp + 1;
+  ia.dH = dLdH;
+  ia.dtype = dtype;
+  HIPCHK(c, launch_bwd_init(bprec, ia, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const auto t_end = std::chrono::steady_clock::now();
+  if (res) {
+    std::memset(res, 0, sizeof(*res));
+    res->status = GCP_OK;
+    res->iters = p;
+    res->t1 = res->t2 = res->c_last = res->idem = NAN;
+    res->ms_total = std::chrono::duration<double, std::milli>(t_end - t_start).count();
+    res->gemm_launches = nlaunch;
+    res->gemm_flops = flops;
+    res->mfma_flops = mflops;
+    double ms = 0.0;
+    if (prof) {
+      for (int k = 0; k < nlaunch; ++k) {
+        float t = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&t, c->events[2 * k], c->events[2 * k + 1]));
+        ms += t;
+      }
+    }
+    res->gemm_ms = ms;
+  }
+  return GCP_OK;
 }
 
 extern "C" int gcp_get_history(const gcp_ctx *c, double *rows, int32_t max_rows,

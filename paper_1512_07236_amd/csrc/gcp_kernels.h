@@ -71,6 +71,43 @@ struct OutArgs {
   int dtype;
 };
 
+// Adjoint of one update (gcp_backward.hip).  All matrices are Mp x Mp
+// row-major in the adjoint's storage type (FP64 or FP32).
+struct BwdArgs {
+  const void *D;       // D_n
+  const void *X2;      // D_n^2                     (modes 1, 2)
+  const void *G;       // Gbar_{n+1} = dL/dD_{n+1}
+  const void *AT;      // D_n Gbar_{n+1}            (mode 2)
+  const void *CT;      // D_n^2 Gbar_{n+1}          (mode 2)
+  void *out0;          // mode 0: X2; mode 1: AT; mode 2: Gbar_n
+  void *out1;          // mode 1: CT
+  int64_t Mp;
+  int nt;
+  int mode;            // 0: X2 = D D; 1: AT = D G and CT = X2 G; 2: E = D G D + combine
+  double a, b, c, inv_t12;   // 1 - 2c_n, 2 + 2c_n, c_n, 1 / (T1 - T2)_n
+  const double *kappa; // device scalar (mode 2)
+  double *tpart;       // mode 0: per-tile sums of w_ij G_ij (X2_ij - D_ij)
+};
+
+struct BwdInitArgs {
+  const void *G0;      // Gbar_0 (Mp x Mp)
+  const void *D0;      // D_0 (Mp x Mp)
+  int64_t M, Mp, ldh;
+  double beta, dbeta, theta;
+  double *rows;        // 2 Mp scratch: row sums of G0 o D0, diag of G0
+  double *sums;        // 2 scalars
+  void *dH;            // output, M x M with leading dimension ldh
+  int dtype;
+};
+
+hipError_t launch_bwd_store(int fprec, int bprec, const void *planes, const double *dg,
+                            int64_t Mp, void *out, hipStream_t st);
+hipError_t launch_bwd_load(int bprec, const void *g, int64_t ldg, int dtype, int64_t M,
+                           int64_t Mp, void *G, hipStream_t st);
+hipError_t launch_bwd_gemm(int bprec, const BwdArgs &a, hipStream_t st);
+hipError_t launch_bwd_kappa(const double *tpart, int n, double *kappa, hipStream_t st);
+hipError_t launch_bwd_init(int bprec, const BwdInitArgs &a, hipStream_t st);
+
 hipError_t launch_gemm(int prec, const GemmArgs &g, hipStream_t st);
 // Blocks of the 16-bit product kernel (pairs of 128 x 128 tiles) for nt tiles per side.
 int pair_count(int nt);

@@ -19,79 +19,9 @@
 
 #include "gcp_encode.h"
 #include "gcp_kernels.h"
+#include "gcp_mma.h"
 
 namespace gcp {
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef _Float16 v8h __attribute__((ext_vector_type(8)));
-typedef __bf16 v8b __attribute__((ext_vector_type(8)));
-typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-
-constexpr int TILE = 128;   // output tile edge
-constexpr int NTH = 256;    // threads per tile: 4 waves in a 2 x 2 grid of 64 x 64
-
-template <int KIND> struct AccType { using type = v4f; };
-template <> struct AccType<0> { using type = v4d; };
-
-// 16x16 output block per MFMA; lane l holds column l%16 and four rows r = 0..3:
-// rows 4*(l/16)+r for the FP32-accumulating instructions, rows (l/16)+4r for
-// the FP64 one.  A/B fragments: lane l supplies row l%16 of its operand at K
-// offsets determined by l/16 (the same for A and B, so the K order inside an
-// instruction never matters).
-template <int KIND>
-__device__ __forceinline__ int acc_row(int lg, int r) {
-  return KIND == 0 ? lg + 4 * r : 4 * lg + r;
-}
-__device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-template <int KIND>
-__device__ __forceinline__ v4f mfma16(v4u a, v4u b, v4f c) {
-  if constexpr (KIND == 2)
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8b, a),
-                                                   __builtin_bit_cast(v8b, b), c, 0, 0, 0);
-  else
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a),
-                                                  __builtin_bit_cast(v8h, b), c, 0, 0, 0);
-}
-
-__device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
-
-// Upper-triangle tile of block b.  Tiles are ordered in G x G groups of the
-// tile grid (the diagonal groups are triangular), row-major inside a group.
-// Blocks are dispatched round-robin over the 8 XCDs; each XCD gets a
-// contiguous run of that order, so the ~64 tiles resident on one XCD at a
-// time fall in one group and read about 2G row panels, which its L2 serves.
-constexpr int TILE_GROUP = 8;
-
-__device__ __forceinline__ void tile_of_block(int b, int nt, int &ti, int &tj, int &lin) {
-  const int ntiles = nt * (nt + 1) / 2;
-  const int xcd = b & 7, loc = b >> 3, q = ntiles >> 3, r = ntiles & 7;
-  int L = xcd * q + (xcd < r ? xcd : r) + loc;
-  lin = L;
-  const int ng = (nt + TILE_GROUP - 1) / TILE_GROUP;
-  for (int gr = 0; gr < ng; ++gr) {
-    const int r0 = gr * TILE_GROUP, r1 = min(nt, r0 + TILE_GROUP);
-    for (int gc = gr; gc < ng; ++gc) {
-      const int c0 = gc * TILE_GROUP, c1 = min(nt, c0 + TILE_GROUP);
-      for (int t = r0; t < r1; ++t) {
-        const int first = (gc == gr) ? t : c0;   // diagonal group: tj >= ti
-        const int len = c1 - first;
-        if (L < len) {
-          ti = t;
-          tj = first + L;
-          return;
-        }
-        L -= len;
-      }
-    }
-  }
-  ti = tj = 0;   // not reached for b < ntiles
-}
 
 // FP64 / FP32 product kernel: one 128 x 128 upper-triangle tile per block of
 // 4 waves (2 x 2 grid of 64 x 64), MFMA 16x16x4, two blocks per CU.
@@ -100,15 +30,9 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
   using E = Enc<P>;
   using T = typename E::T;
   constexpr int NP = E::NP, KIND = E::KIND;
-  constexpr int ES = sizeof(T);
-  constexpr int KT = 128 / ES;                    // K per LDS stage
-  constexpr int EPC = 16 / ES;                    // elements per 16-byte chunk
-  constexpr int LDR = KT + EPC;                   // LDS row stride (one chunk of padding)
-  constexpr int CPR = KT / EPC;                   // chunks per row per plane
-  constexpr int CPT = TILE * CPR / NTH;           // chunks per thread per operand per plane
   using Acc = typename AccType<KIND>::type;
 
-  __shared__ __attribute__((aligned(16))) T smem[2 * NP * TILE * LDR];
+  __shared__ __attribute__((aligned(16))) T smem[MmaCfg<P>::SMEM];
 
   int ti, tj, lin;
   tile_of_block(blockIdx.x, g.nt, ti, tj, lin);
@@ -119,65 +43,8 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1, l16 = lane & 15, lg = lane >> 4;
 
-  T *As = smem;
-  T *Bs = smem + NP * TILE * LDR;
-
-  v4u ra[NP][CPT], rb[NP][CPT];
-  auto gload = [&](int kt) {
-    const int64_t k0 = (int64_t)kt * KT;
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int c = 0; c < CPT; ++c) {
-        const int ch = tid + c * NTH, row = ch / CPR, kc = ch % CPR;
-        ra[p][c] = *(const v4u *)(Ag + p * PS + (arow0 + row) * Mp + k0 + kc * EPC);
-        rb[p][c] = *(const v4u *)(Bg + p * PS + (brow0 + row) * Mp + k0 + kc * EPC);
-      }
-  };
-  auto swrite = [&]() {
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int c = 0; c < CPT; ++c) {
-        const int ch = tid + c * NTH, row = ch / CPR, kc = ch % CPR;
-        *(v4u *)(As + (p * TILE + row) * LDR + kc * EPC) = ra[p][c];
-        *(v4u *)(Bs + (p * TILE + row) * LDR + kc * EPC) = rb[p][c];
-      }
-  };
-
-  static_assert(KIND <= 1, "16-bit encodings use k_gemm16");
   Acc acc0[4][4];
-#pragma unroll
-  for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 4; ++bj) acc0[bi][bj] = Acc{};
-
-  const int nk = (int)(Mp / KT);
-  gload(0);
-  swrite();
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk) gload(kt + 1);
-    {
-#pragma unroll
-      for (int ks = 0; ks < KT / 4; ++ks) {
-        T bf[4];
-#pragma unroll
-        for (int bj = 0; bj < 4; ++bj) bf[bj] = Bs[(wn * 64 + bj * 16 + l16) * LDR + ks * 4 + lg];
-#pragma unroll
-        for (int bi = 0; bi < 4; ++bi) {
-          const T af = As[(wm * 64 + bi * 16 + l16) * LDR + ks * 4 + lg];
-#pragma unroll
-          for (int bj = 0; bj < 4; ++bj) acc0[bi][bj] = mfma(af, bf[bj], acc0[bi][bj]);
-        }
-      }
-    }
-    __syncthreads();
-    if (kt + 1 < nk) {
-      swrite();
-      __syncthreads();
-    }
-  }
+  mma_tile<P>(Ag, Bg, arow0, brow0, Mp, PS, smem, acc0);
 
   // ------------------------------------------------------------ epilogue
   const double S = E::PROD_SCALE;

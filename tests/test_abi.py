@@ -25,8 +25,8 @@ def lib():
 
 def test_header_declares_the_boundary():
     syms = declared_symbols()
-    for s in ("gcp_create", "gcp_init", "gcp_purify", "gcp_destroy", "gcp_get_history",
-              "gcp_last_error", "gcp_options_default"):
+    for s in ("gcp_create", "gcp_init", "gcp_purify", "gcp_backward", "gcp_destroy",
+              "gcp_get_history", "gcp_last_error", "gcp_options_default"):
         assert s in syms
 
 
@@ -42,22 +42,23 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "gcp.h"\n'
-        'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(gcp_options), sizeof(gcp_result),'
-        ' offsetof(gcp_options, fold_every), offsetof(gcp_result, gemm_launches),'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(gcp_options),'
+        ' sizeof(gcp_result), offsetof(gcp_options, fold_every),'
+        ' offsetof(gcp_options, bwd_precision), offsetof(gcp_result, gemm_launches),'
         ' offsetof(gcp_result, mfma_flops));return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     assert got == [ctypes.sizeof(gcp.Options), ctypes.sizeof(gcp.CResult),
-                   gcp.Options.fold_every.offset, gcp.CResult.gemm_launches.offset,
-                   gcp.CResult.mfma_flops.offset]
+                   gcp.Options.fold_every.offset, gcp.Options.bwd_precision.offset,
+                   gcp.CResult.gemm_launches.offset, gcp.CResult.mfma_flops.offset]
 
 
 def test_options_default(lib):
     import paper_1512_07236_amd as gcp
     o = gcp.default_options()
-    assert (o.precision, o.max_iter, o.tol_ddbar, o.tol_idem, o.fold_every, o.profile) == \
-        (0, 100, 1e-6, 0.0, 0, 0)
+    assert (o.precision, o.max_iter, o.tol_ddbar, o.tol_idem, o.fold_every, o.profile,
+            o.keep_iterates, o.bwd_precision) == (0, 100, 1e-6, 0.0, 0, 0, 0, 0)
     assert lib.gcp_options_default(None) == gcp.ERR_INVALID_ARG
 
 
@@ -73,10 +74,16 @@ def test_create_rejects_bad_arguments_before_touching_the_device(lib):
     o = gcp.default_options()
     o.tol_ddbar = -1.0
     assert lib.gcp_create(ctypes.byref(h), 16, ctypes.byref(o), None) == gcp.ERR_INVALID_ARG
+    for field, bad in (("keep_iterates", 2), ("bwd_precision", int(gcp.Precision.BF16))):
+        o = gcp.default_options()
+        setattr(o, field, bad)
+        assert lib.gcp_create(ctypes.byref(h), 16, ctypes.byref(o), None) == gcp.ERR_INVALID_ARG
+        assert b"bwd_precision" in lib.gcp_last_error(None)
     assert h.value is None
     # NULL contexts are rejected, not dereferenced
     assert lib.gcp_init(None, None, 16, 1, 0.0, 1.0) == gcp.ERR_INVALID_ARG
     assert lib.gcp_purify(None, None, 0, 16, None) == gcp.ERR_INVALID_ARG
+    assert lib.gcp_backward(None, None, 16, None, 16, 0, None) == gcp.ERR_INVALID_ARG
     n = ctypes.c_int32()
     assert lib.gcp_get_history(None, None, 0, ctypes.byref(n)) == gcp.ERR_INVALID_ARG
     lib.gcp_destroy(None)

@@ -269,6 +269,10 @@ def test_full_size_spectral_8192(config3, precision, tol_ddbar, err_tol):
     assert err < err_tol
     n = min(res.iters, s["iters"])
     ddbar = (res.col("t1") - res.col("t2"))[:n]
-    ctol = 1e-11 if precision == "fp64" else 1e-4
-    assert np.all(np.abs(res.col("c")[:n] - s["c"][:n]) <= ctol + 1e-12 / np.abs(ddbar))
+    # c_n = (T2 - T3)/(T1 - T2): an absolute error e in the traces of the
+    # iterate moves c_n by about e/(T1 - T2).  FP64: e ~ 1e-12 (summation);
+    # the split encodings carry ~2^-22 relative error per element, which
+    # measured as e ~ 8e-7 at M = 8192, N = 3000 (bound: 1e-5).
+    ctol, cnum = (1e-11, 1e-12) if precision == "fp64" else (1e-4, 1e-5)
+    assert np.all(np.abs(res.col("c")[:n] - s["c"][:n]) <= ctol + cnum / np.abs(ddbar))
     assert abs(res.iters - s["iters"]) <= (0 if precision == "fp64" else 1)
