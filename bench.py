@@ -12,7 +12,8 @@ Reported: throughput of the mixed-precision path in algorithmic TFLOP/s
 its time to solution, the FP64 GPU path's time to solution on the same input,
 both errors ||D - D_ref||_F / sqrt(M) against the closed-form projector, the
 roofline of the dominant kernel (the product kernel) and the CPU oracle timed
-on a bounded sample of the same workload.
+on a bounded sample of the same workload.  The adjoint of the mixed solve
+(gcp_backward in FP32, loss u^T D u) is timed alongside as extra information.
 """
 from __future__ import annotations
 
@@ -150,6 +151,8 @@ def main() -> int:
                     help="|Tr(D Dbar)| stop; default 1e-5 for the split 16-bit encodings "
                          "(their rounding floor at M=8192 is ~1e-6) and 1e-6 otherwise")
     ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--bwd-steps", type=int, default=1,
+                    help="timed adjoints (gcp_backward, FP32) of the mixed solve for L = u^T D u")
     ap.add_argument("--scale", type=int, default=1, help="divide M by this (quick runs only)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -243,6 +246,31 @@ def main() -> int:
                 / (g64 * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"]}
         log(f"[bench] FP64: {t64*1e3:.1f} ms/solve, iters={res64[-1].iters}, err={err64:.3e}")
 
+    bwd = None
+    if args.bwd_steps > 0:
+        log(f"[bench] adjoint of the {prec.name} solve (FP32): {args.bwd_steps} timed")
+        ctx = gcp.Context(M, precision=prec, tol_ddbar=tol_for(prec), max_iter=100,
+                          fold_every=args.fold_every, profile=True, keep_iterates=True,
+                          bwd_precision="fp32")
+        ctx.init(H, N, w.emin, w.emax)
+        ctx.purify()
+        u = torch.from_numpy(np.random.default_rng(33).standard_normal(M)).cuda()
+        G = torch.outer(u, u)
+        ctx.backward(G)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.bwd_steps):
+            _, rb = ctx.backward(G)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / args.bwd_steps
+        ctx.close()
+        bwd = {"precision": "fp32", "updates": rb.iters, "ms": tb * 1e3,
+               "tflops": rb.gemm_flops / tb / 1e12,
+               "gemm_ms_per_launch": rb.gemm_ms / max(rb.gemm_launches, 1),
+               "gemm_frac_of_fp32_peak": rb.gemm_flops / (rb.gemm_ms * 1e-3) / 1e12
+               / PEAK_TFLOPS["fp32"]}
+        log(f"[bench] adjoint: {tb*1e3:.1f} ms, {bwd['tflops']:.1f} TFLOP/s")
+
     if args.copy_calibration:
         copy_calibration()
 
@@ -275,6 +303,7 @@ def main() -> int:
         "meets_1e-6": bool(err_m <= 1e-6 and tr_m <= 1e-10),
         "fp64": fp64,
         "speedup_vs_fp64": (fp64["time_to_solution_ms"] / (t_mixed * 1e3)) if fp64 else None,
+        "backward": bwd,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": (f"k_gemm16<{prec.name}>" if gcp.MFMA_DTYPE[prec] in ("fp16", "bf16")

@@ -24,7 +24,15 @@ struct GemmArgs {
   int nt;              // Mp / 128
   int mode;            // 0: X2 = D D, 1: D_{n+1} = (1-2c) D + (2+2c) X2 - 2 X2 D
   int fold;            // fold period of the main accumulator, in K stages
+  // 16-bit kernel: blocks [0, nfull) compute whole pairs; the remaining pairs
+  // are each split over nsplit blocks along K (nsplit = 1: no split), whose
+  // FP32 partial tiles meet in ws and are added, in split order, by the
+  // last of them to finish (per-pair arrival counters in cnt, self-resetting)
+  int nfull;
+  int nsplit;
   int pad;
+  float *ws;
+  unsigned *cnt;
   const double *dg;    // diag(D) FP64
   const double *rD;    // diag(D) - dec(enc(diag(D)))
   const double *d2;    // diag(X2) FP64
@@ -111,6 +119,8 @@ hipError_t launch_bwd_init(int bprec, const BwdInitArgs &a, hipStream_t st);
 hipError_t launch_gemm(int prec, const GemmArgs &g, hipStream_t st);
 // Blocks of the 16-bit product kernel (pairs of 128 x 128 tiles) for nt tiles per side.
 int pair_count(int nt);
+// Grid of the 16-bit product kernel: whole pairs plus the K-split tail blocks.
+int gemm16_blocks(const GemmArgs &g);
 hipError_t launch_init(int prec, const InitArgs &a, hipStream_t st);
 hipError_t launch_output(int prec, const OutArgs &a, hipStream_t st);
 hipError_t launch_reduce(const RedArgs &a, hipStream_t st);

@@ -262,8 +262,18 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
   constexpr int SMEM = NBUF * STAGE > EPI ? NBUF * STAGE : EPI;
   __shared__ __attribute__((aligned(16))) T smem[SMEM];
 
-  int ti, cpair, lin;
-  pair_of_block(blockIdx.x, g.nt, ti, cpair, lin);
+  // whole pair, or split s of a tail pair over K stages [kbase, kbase + nk)
+  const int nk_all = (int)(R128 ? g.Mp * NP / 64 : g.Mp / KT);
+  int ti, cpair, lin, split = -1, kbase = 0, nk = nk_all;
+  if ((int)blockIdx.x < g.nfull) {
+    pair_of_block(blockIdx.x, g.nt, ti, cpair, lin);
+  } else {
+    const int u = (int)blockIdx.x - g.nfull;
+    split = u % g.nsplit;
+    pair_of_block(g.nfull + u / g.nsplit, g.nt, ti, cpair, lin);
+    kbase = split * nk_all / g.nsplit;
+    nk = (split + 1) * nk_all / g.nsplit - kbase;
+  }
   const int64_t Mp = g.Mp, PS = g.pstride;
   const int64_t arow0 = (int64_t)ti * TILE, brow0 = (int64_t)cpair * BR;
   const T *__restrict__ Ag = (const T *)g.A;
@@ -294,14 +304,14 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
         const int R = blk * 8 + (lane >> 3);
         const int c = (lane & 7) ^ swz(R);
         const T *src = (R < AR ? Ag + (arow0 + R) * (NP * Mp) : Bg + (brow0 + R - AR) * (NP * Mp)) +
-                       (int64_t)kt * 64 + c * 8;
+                       (int64_t)(kbase + kt) * 64 + c * 8;
         __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)(st + blk * 8 * 64), 16, 0, 0);
       } else {
         const int p = blk / ((AR + BR) / 16), gq = blk % ((AR + BR) / 16);
         const int R = gq * 16 + (lane >> 2);
         const int c = (lane & 3) ^ swz(R);
         const T *src = (R < AR ? Ag + p * PS + (arow0 + R) * Mp : Bg + p * PS + (brow0 + R - AR) * Mp) +
-                       (int64_t)kt * KT + c * 8;
+                       (int64_t)(kbase + kt) * KT + c * 8;
         __builtin_amdgcn_global_load_lds((const void *)src,
                                          (lds_void *)(st + (p * (AR + BR) + gq * 16) * KT), 16, 0, 0);
       }
@@ -333,7 +343,6 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
   constexpr int PB[6] = {0, 1, 0, 1, 2, 0};
   constexpr int QA[2] = {0, 1};
 
-  const int nk = (int)(R128 ? Mp * NP / 64 : Mp / KT);
   const int fold = g.fold;   // >= 1 (resolved on the host)
   // Waves of a tile below the diagonal run the same instruction stream (their
   // results are discarded): the loop body stays branch-free, which keeps the
@@ -387,6 +396,50 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
       }
   }
   __syncthreads();   // all waves done with the stage buffers (reused below)
+
+  if (split >= 0) {
+    // K-split tail pair: publish this split's FP32 totals; the last split to
+    // arrive adds all of them in split order (so the sum does not depend on
+    // the arrival order) and runs the epilogue.
+    constexpr int NV = 4 * NBJ;   // float4 per thread
+    const int q = (int)blockIdx.x - g.nfull;
+    const int pair = q / g.nsplit;
+    float4 *wsp = (float4 *)g.ws + (int64_t)q * NV * NTH16;
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < NBJ; ++bj) {
+        const v4f t = tot[bi][bj];
+        wsp[(bi * NBJ + bj) * NTH16 + tid] = make_float4(t[0], t[1], t[2], t[3]);
+      }
+    __threadfence();
+    // The arrival flag lives in the (now idle) stage buffers: a second
+    // __shared__ object would make the compiler wait for every LDS-DMA load
+    // before each LDS read of the main loop (it cannot tell them apart).
+    unsigned *last = (unsigned *)smem;
+    __syncthreads();
+    if (tid == 0) *last = (atomicAdd(g.cnt + pair, 1u) == (unsigned)g.nsplit - 1);
+    __syncthreads();
+    if (!*last) return;
+    __syncthreads();   // flag read by all before the epilogue reuses smem
+    __threadfence();
+    const float4 *w0 = (const float4 *)g.ws + (int64_t)pair * g.nsplit * NV * NTH16;
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < NBJ; ++bj) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int s = 0; s < g.nsplit; ++s) {
+          const float4 v = w0[((int64_t)s * NV + bi * NBJ + bj) * NTH16 + tid];
+          a0 += v.x;
+          a1 += v.y;
+          a2 += v.z;
+          a3 += v.w;
+        }
+        tot[bi][bj] = v4f{(float)a0, (float)a1, (float)a2, (float)a3};
+      }
+    if (tid == 0) g.cnt[pair] = 0u;   // ready for the next launch
+  }
 
   // ------------------------------------------------------------ epilogue
   // Phase 0: every wave dumps its FP32 results into LDS, V[tile][row][col]
@@ -594,6 +647,11 @@ int pair_count(int nt) {
   int n = 0;
   for (int t = 0; t < nt; ++t) n += nt / PAIR_COLS - t / PAIR_COLS;
   return n;
+}
+
+int gemm16_blocks(const GemmArgs &g) {
+  const int np = pair_count(g.nt);
+  return g.nfull + (np - g.nfull) * g.nsplit;
 }
 
 // ------------------------------------------------------------------ H stats
@@ -828,7 +886,7 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a) {
 template <int P>
 static hipError_t launch_gemm_p(const GemmArgs &g, int ntiles, hipStream_t st) {
   if constexpr (Enc<P>::KIND >= 2)
-    k_gemm16<P><<<pair_count(g.nt), NTH16, 0, st>>>(g);
+    k_gemm16<P><<<gemm16_blocks(g), NTH16, 0, st>>>(g);
   else
     k_gemm<P><<<ntiles, NTH, 0, st>>>(g);
   return hipGetLastError();
