@@ -13,7 +13,9 @@ its time to solution, the FP64 GPU path's time to solution on the same input,
 both errors ||D - D_ref||_F / sqrt(M) against the closed-form projector, the
 roofline of the dominant kernel (the product kernel) and the CPU oracle timed
 on a bounded sample of the same workload.  The adjoint of the mixed solve
-(gcp_backward in FP32, loss u^T D u) is timed alongside as extra information.
+(gcp_backward in FP32, loss u^T D u) and the FP64 acceptance checks of its
+result (gcp_verify: trace, idempotency, energy against the sum of the N lowest
+eigenvalues, commutator with H) are reported alongside as extra information.
 """
 from __future__ import annotations
 
@@ -246,6 +248,17 @@ def main() -> int:
                 / (g64 * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"]}
         log(f"[bench] FP64: {t64*1e3:.1f} ms/solve, iters={res64[-1].iters}, err={err64:.3e}")
 
+    log("[bench] FP64 acceptance checks of the mixed result (gcp_verify)")
+    with gcp.Context(M, precision=prec, tol_ddbar=tol_for(prec), max_iter=100,
+                     fold_every=args.fold_every) as vctx:
+        vctx.init(H, N, w.emin, w.emax)
+        Dv, _ = vctx.purify()
+        vctx.verify(Dv, H)   # warm-up (allocates the workspace)
+        q = vctx.verify(Dv, H)
+    e0 = float(np.sort(w.lam)[:N].sum())
+    verify = {"ms": q["ms"], "trace_err": abs(q["trace"] - N), "fro2_minus_N": q["fro2"] - N,
+              "idem": q["idem"], "energy_err": q["energy"] - e0, "comm": q["comm"]}
+
     bwd = None
     if args.bwd_steps > 0:
         log(f"[bench] adjoint of the {prec.name} solve (FP32): {args.bwd_steps} timed")
@@ -304,6 +317,7 @@ def main() -> int:
         "fp64": fp64,
         "speedup_vs_fp64": (fp64["time_to_solution_ms"] / (t_mixed * 1e3)) if fp64 else None,
         "backward": bwd,
+        "verify": verify,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": (f"k_gemm16<{prec.name}>" if gcp.MFMA_DTYPE[prec] in ("fp16", "bf16")

@@ -161,6 +161,28 @@ int gcp_purify(gcp_ctx *ctx, void *D, int32_t dtype, int64_t ldd, gcp_result *ou
 int gcp_backward(gcp_ctx *ctx, const void *dL_dD, int64_t ldg, void *dL_dH, int64_t ldh,
                  int32_t dtype, gcp_result *out);
 
+/* Checks of a density matrix D against H, all in FP64 (MFMA products and
+ * fixed-order sums); neither matrix needs to come from this context.
+ * D (M x M, leading dimension ldd, dtype gcp_dtype) and H (FP64, M x M,
+ * leading dimension ldh) are device pointers on the context's GPU, read as
+ * their symmetric parts.  The values are those the paper uses to accept a
+ * converged density matrix (the tests after the convergence discussion):
+ *   trace     Tr D (N for the ground-state projector)
+ *   fro2      ||D||_F^2 (also N for a projector)
+ *   idem      ||D^2 - D||_F
+ *   energy    Tr(D H) (the sum of the N lowest eigenvalues at the ground state)
+ *   comm      ||H D - D H||_F
+ * Work: two M^3-class FP64 products (D^2 on upper tiles, H D on all tiles).
+ * The first call allocates three M x M FP64 matrices of workspace, kept by
+ * the context.  Errors: INVALID_ARG for NULL pointers, ld < M or a bad dtype;
+ * NO_MEMORY if the workspace cannot be allocated. */
+typedef struct {
+    double trace, fro2, idem, energy, comm;
+    double ms;           /* host wall time of the call */
+} gcp_verify_result;
+int gcp_verify(gcp_ctx *ctx, const void *D, int32_t dtype, int64_t ldd, const double *H,
+               int64_t ldh, gcp_verify_result *out);
+
 /* Per-iterate history of the last gcp_purify: GCP_HIST_COLS doubles per row,
  *   [n, Tr D, Tr D^2, Tr D^3, c_n, Omega = ||D^2-D||_F^2, gamma_n = (1-2c_n)/3,
  *    L_n = Omega - gamma_n (3 Tr D^2 - 2 Tr D^3 - N) (eq. mcw4b), ||D_{n+1} - D_n||_F]

@@ -202,6 +202,17 @@ def projector_from_spectrum(Q: np.ndarray, lam: np.ndarray, N: int) -> np.ndarra
     return Qo @ Qo.T
 
 
+def verify_quantities(D: np.ndarray, H: np.ndarray) -> dict:
+    """The acceptance quantities of a density matrix, by their definitions
+    (FP64, library matmuls): Tr D, ||D||_F^2, ||D^2 - D||_F, Tr(DH) and
+    ||HD - DH||_F, for the symmetric parts of D and H."""
+    D = 0.5 * (_f64(D) + _f64(D).T)
+    H = 0.5 * (_f64(H) + _f64(H).T)
+    return {"trace": float(np.trace(D)), "fro2": float(np.sum(D * D)),
+            "idem": float(np.linalg.norm(D @ D - D)), "energy": float(np.sum(D * H)),
+            "comm": float(np.linalg.norm(H @ D - D @ H))}
+
+
 def scalar_map(eps: np.ndarray, N: int, emin: float, emax: float, mu: Optional[float] = None,
                tol_ddbar: float = 1e-6, tol_idem: float = 0.0, max_iter: int = 100):
     """The recursion on eigenvalues (H with known spectrum eps).

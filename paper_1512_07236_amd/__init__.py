@@ -79,6 +79,11 @@ class CResult(ctypes.Structure):
                 ("mfma_flops", ctypes.c_double)]
 
 
+class CVerify(ctypes.Structure):
+    _fields_ = [("trace", ctypes.c_double), ("fro2", ctypes.c_double), ("idem", ctypes.c_double),
+                ("energy", ctypes.c_double), ("comm", ctypes.c_double), ("ms", ctypes.c_double)]
+
+
 class GCPError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -110,6 +115,8 @@ def load_library() -> ctypes.CDLL:
     L.gcp_purify.restype = ctypes.c_int
     L.gcp_backward.argtypes = [vp, vp, i64, vp, i64, i32, ctypes.POINTER(CResult)]
     L.gcp_backward.restype = ctypes.c_int
+    L.gcp_verify.argtypes = [vp, vp, i32, i64, vp, i64, ctypes.POINTER(CVerify)]
+    L.gcp_verify.restype = ctypes.c_int
     L.gcp_get_history.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32)]
     L.gcp_get_history.restype = ctypes.c_int
     L.gcp_get_init_scalars.argtypes = [vp] + [ctypes.POINTER(ctypes.c_double)] * 4
@@ -238,6 +245,20 @@ class Context:
                                          out.stride(0), dt, ctypes.byref(r)))
         return out, Result(r.status, r.iters, r.t1, r.t2, r.c_last, r.idem, r.ms_total, r.gemm_ms,
                            r.gemm_launches, r.gemm_flops, r.mfma_flops, np.zeros((0, HIST_COLS)))
+
+    def verify(self, D, H) -> dict:
+        """FP64 checks of D against H on the GPU: Tr D, ||D||_F^2, ||D^2 - D||_F,
+        Tr(DH), ||HD - DH||_F (and the call's wall time in ms)."""
+        import torch
+        for name, X, dts in (("D", D, (torch.float64, torch.float32)), ("H", H, (torch.float64,))):
+            if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype in dts and
+                    X.stride(1) == 1 and tuple(X.shape) == (self.M, self.M)):
+                raise ValueError(f"{name} must be an M x M CUDA tensor of {dts} with unit column stride")
+        dt = DTYPE_F64 if D.dtype == torch.float64 else DTYPE_F32
+        r = CVerify()
+        self._check(self._L.gcp_verify(self._h, ctypes.c_void_p(D.data_ptr()), dt, D.stride(0),
+                                       ctypes.c_void_p(H.data_ptr()), H.stride(0), ctypes.byref(r)))
+        return {k: getattr(r, k) for k, _ in CVerify._fields_}
 
     def history(self) -> np.ndarray:
         n = ctypes.c_int32()

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libgcp.so")
-SOURCES = ["gcp_api.hip", "gcp_kernels.hip", "gcp_backward.hip"]
+SOURCES = ["gcp_api.hip", "gcp_kernels.hip", "gcp_backward.hip", "gcp_verify.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -88,6 +88,8 @@ struct gcp_ctx {
   void *bX2 = nullptr, *bAT = nullptr, *bCT = nullptr;
   double *btpart = nullptr; // upper-tile partial sums
   double *bvec = nullptr;   // 2 Mp row scratch + kappa + 2 sums
+  // verification workspace (allocated by the first gcp_verify)
+  double *vD = nullptr, *vH = nullptr, *vHD = nullptr, *vaux = nullptr;
   // profiling
   std::vector<hipEvent_t> events;
   std::string err;
@@ -114,7 +116,7 @@ static void free_all(gcp_ctx *c) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   void *bptrs[] = {c->bG[0], c->bG[1], c->bX2, c->bAT, c->bCT, c->btpart, c->bvec, c->g16_ws,
-                   c->g16_cnt};
+                   c->g16_cnt, c->vD, c->vH, c->vHD, c->vaux};
   for (void *p : bptrs)
     if (p) (void)hipFree(p);
   for (void *p : c->slots)
@@ -695,6 +697,59 @@ extern "C" int gcp_backward(gcp_ctx *c, const void *dLdD, int64_t ldg, void *dLd
       }
     }
     res->gemm_ms = ms;
+  }
+  return GCP_OK;
+}
+
+extern "C" int gcp_verify(gcp_ctx *c, const void *D, int32_t dtype, int64_t ldd, const double *H,
+                          int64_t ldh, gcp_verify_result *res) {
+  if (!c) return GCP_ERR_INVALID_ARG;
+  if (!D || !H || ldd < c->M || ldh < c->M || (dtype != GCP_DTYPE_F64 && dtype != GCP_DTYPE_F32)) {
+    c->err = "gcp_verify: need non-NULL D and H, ldd >= M, ldh >= M and dtype F64 or F32";
+    return GCP_ERR_INVALID_ARG;
+  }
+  const auto t_start = std::chrono::steady_clock::now();
+  const size_t Mp = (size_t)c->Mp, mat = Mp * Mp * sizeof(double);
+  const int ntri = c->nt * (c->nt + 1) / 2;
+  if (!c->vD) {
+    void *p[4] = {nullptr, nullptr, nullptr, nullptr};
+    const size_t sz[4] = {mat, mat, mat, (4 * Mp + (size_t)ntri + 8) * sizeof(double)};
+    for (int k = 0; k < 4; ++k) {
+      if (hipMalloc(&p[k], sz[k]) != hipSuccess) {
+        for (int q = 0; q < k; ++q) (void)hipFree(p[q]);
+        c->err = "gcp_verify: device allocation of the workspace failed";
+        return GCP_ERR_NO_MEMORY;
+      }
+    }
+    c->vD = (double *)p[0];
+    c->vH = (double *)p[1];
+    c->vHD = (double *)p[2];
+    c->vaux = (double *)p[3];
+  }
+  HIPCHK(c, launch_bwd_load(GCP_FP64, D, ldd, dtype, c->M, c->Mp, c->vD, c->stream));
+  HIPCHK(c, launch_bwd_load(GCP_FP64, H, ldh, GCP_DTYPE_F64, c->M, c->Mp, c->vH, c->stream));
+  VerifyArgs a{};
+  a.D = c->vD;
+  a.H = c->vH;
+  a.HD = c->vHD;
+  a.rows = c->vaux;
+  a.tpart = c->vaux + 4 * Mp;
+  a.out = c->vaux + 4 * Mp + ntri;
+  a.Mp = c->Mp;
+  a.nt = c->nt;
+  a.ntri = ntri;
+  HIPCHK(c, launch_verify(a, c->stream));
+  double out[5];
+  HIPCHK(c, hipMemcpyAsync(out, a.out, sizeof(out), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const auto t_end = std::chrono::steady_clock::now();
+  if (res) {
+    res->comm = std::sqrt(2.0 * out[0]);   // each off-diagonal pair counted once
+    res->energy = out[1];
+    res->fro2 = out[2];
+    res->trace = out[3];
+    res->idem = std::sqrt(out[4]);
+    res->ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
   }
   return GCP_OK;
 }

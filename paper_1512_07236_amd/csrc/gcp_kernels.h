@@ -108,6 +108,19 @@ struct BwdInitArgs {
   int dtype;
 };
 
+// FP64 verification of a density matrix (gcp_verify.hip).  D and H are the
+// symmetric parts of the caller's matrices, Mp x Mp, zero padded.
+struct VerifyArgs {
+  const double *D, *H;
+  double *HD;          // Mp x Mp
+  double *tpart;       // upper-tile partials of ||D^2 - D||_F^2
+  double *rows;        // 4 Mp row partials
+  double *out;         // 5 sums: commutator^2, Tr(DH), ||D||_F^2, Tr D, ||D^2-D||_F^2
+  int64_t Mp;
+  int nt, ntri;
+};
+hipError_t launch_verify(const VerifyArgs &a, hipStream_t st);
+
 hipError_t launch_bwd_store(int fprec, int bprec, const void *planes, const double *dg,
                             int64_t Mp, void *out, hipStream_t st);
 hipError_t launch_bwd_load(int bprec, const void *g, int64_t ldg, int dtype, int64_t M,

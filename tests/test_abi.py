@@ -42,14 +42,16 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "gcp.h"\n'
-        'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(gcp_options),'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gcp_options),'
+        ' sizeof(gcp_verify_result), offsetof(gcp_verify_result, ms),'
         ' sizeof(gcp_result), offsetof(gcp_options, fold_every),'
         ' offsetof(gcp_options, bwd_precision), offsetof(gcp_result, gemm_launches),'
         ' offsetof(gcp_result, mfma_flops));return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
-    assert got == [ctypes.sizeof(gcp.Options), ctypes.sizeof(gcp.CResult),
+    assert got == [ctypes.sizeof(gcp.Options), ctypes.sizeof(gcp.CVerify), gcp.CVerify.ms.offset,
+                   ctypes.sizeof(gcp.CResult),
                    gcp.Options.fold_every.offset, gcp.Options.bwd_precision.offset,
                    gcp.CResult.gemm_launches.offset, gcp.CResult.mfma_flops.offset]
 
@@ -84,6 +86,7 @@ def test_create_rejects_bad_arguments_before_touching_the_device(lib):
     assert lib.gcp_init(None, None, 16, 1, 0.0, 1.0) == gcp.ERR_INVALID_ARG
     assert lib.gcp_purify(None, None, 0, 16, None) == gcp.ERR_INVALID_ARG
     assert lib.gcp_backward(None, None, 16, None, 16, 0, None) == gcp.ERR_INVALID_ARG
+    assert lib.gcp_verify(None, None, 0, 16, None, 16, None) == gcp.ERR_INVALID_ARG
     n = ctypes.c_int32()
     assert lib.gcp_get_history(None, None, 0, ctypes.byref(n)) == gcp.ERR_INVALID_ARG
     lib.gcp_destroy(None)

@@ -333,3 +333,26 @@ def test_iteration_counts_against_figure3():
     assert slopes.max() / slopes.min() < g["linearity_slope_ratio_max"]
     lo, hi = g["color_map_range"]
     assert all(lo - wide["abs_tol"] <= x <= hi for x in p)
+
+
+# ---------------------------------------------------------- acceptance checks
+
+def test_verify_quantities_closed_forms(oracle_lib):
+    """Tr D, ||D||_F^2, ||D^2 - D||_F, Tr(DH), ||HD - DH||_F by hand: a diagonal
+    pair, a 2x2 pair with a known commutator, and the ground-state projector of
+    a known spectrum (trace = ||D||_F^2 = N, energy = sum of the N lowest
+    eigenvalues, idempotent, commuting with H)."""
+    d = np.array([0.25, 1.0, -0.5, 2.0])
+    h = np.array([1.0, -2.0, 3.0, 0.5])
+    q = oracle.verify_quantities(np.diag(d), np.diag(h))
+    assert q["trace"] == pytest.approx(2.75) and q["fro2"] == pytest.approx(5.3125)
+    assert q["idem"] == pytest.approx(np.sqrt(np.sum((d * d - d) ** 2)))
+    assert q["energy"] == pytest.approx(0.25 - 2.0 - 1.5 + 1.0) and q["comm"] == 0.0
+    q = oracle.verify_quantities(np.array([[1.0, 0.0], [0.0, 0.0]]), np.array([[0.0, 1.0], [1.0, 0.0]]))
+    assert q["comm"] == pytest.approx(np.sqrt(2.0)) and q["idem"] == 0.0 and q["energy"] == 0.0
+    w = workloads.spectral(64, 20, 0.2, 5)
+    P = oracle.projector_from_spectrum(w.Q, w.lam, w.N)
+    q = oracle.verify_quantities(P, w.H)
+    assert q["trace"] == pytest.approx(20, abs=1e-12) and q["fro2"] == pytest.approx(20, abs=1e-12)
+    assert q["idem"] < 1e-13 and q["comm"] < 1e-13
+    assert q["energy"] == pytest.approx(np.sort(w.lam)[:20].sum(), abs=1e-12)
