@@ -15,7 +15,10 @@ roofline of the dominant kernel (the product kernel) and the CPU oracle timed
 on a bounded sample of the same workload.  The adjoint of the mixed solve
 (gcp_backward in FP32, loss u^T D u) and the FP64 acceptance checks of its
 result (gcp_verify: trace, idempotency, energy against the sum of the N lowest
-eigenvalues, commutator with H) are reported alongside as extra information.
+eigenvalues, commutator with H) are reported alongside as extra information,
+as is a scheduled solve (the mixed encoding, then FP64 once |Tr(D Dbar)| <= 1e-2,
+stopping at 1e-9; near convergence Tr(D Dbar) falls by orders of magnitude per
+update, so the switch must come before the mixed encoding reaches its floor).
 """
 from __future__ import annotations
 
@@ -41,6 +44,20 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
+def product_kernel_hash() -> str:
+    """sha256 of the source the 16-bit product kernel is built from: its text
+    in gcp_kernels.hip and the headers it includes from the package."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1512_07236_amd", "csrc")
+    k = open(os.path.join(csrc, "gcp_kernels.hip")).read()
+    a = k.index("// ------------------------------------------------ 16-bit product kernel")
+    b = k.index("int pair_count(int nt)")
+    h = hashlib.sha256(k[a:b].encode())
+    for f in ("gcp_encode.h", "gcp_mma.h", "gcp_kernels.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
 def pmc_traffic(kernel_tag: str):
     """HBM bytes per launch of the product kernel from the committed rocprofv3
     counter summary (profiles/<kernel_tag>_pmc.json), or None when absent or
@@ -50,9 +67,7 @@ def pmc_traffic(kernel_tag: str):
         return None
     try:
         d = json.load(open(path))
-        import hashlib
-        src = open(os.path.join(ROOT, "paper_1512_07236_amd", "csrc", "gcp_kernels.hip"), "rb").read()
-        if d.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        if d.get("kernel_source_sha256") != product_kernel_hash():
             return None
         return float(d["hbm_bytes_per_launch"])
     except Exception:
@@ -133,8 +148,7 @@ def summarize_pmc(precision: str, scale: int, fetch_dir: str, write_dir: str) ->
                      "copy_kib_raw": max(copy), "copy_factor": factor,
                      "bytes_per_launch": sum(kern) / len(kern) * 1024 / factor}
     out["hbm_bytes_per_launch"] = out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"]
-    src = open(os.path.join(ROOT, "paper_1512_07236_amd", "csrc", "gcp_kernels.hip"), "rb").read()
-    out["kernel_source_sha256"] = hashlib.sha256(src).hexdigest()
+    out["kernel_source_sha256"] = product_kernel_hash()
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     path = os.path.join(ROOT, "profiles", f"{tag}_pmc.json")
     json.dump(out, open(path, "w"), indent=1)
@@ -248,6 +262,26 @@ def main() -> int:
                 / (g64 * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"]}
         log(f"[bench] FP64: {t64*1e3:.1f} ms/solve, iters={res64[-1].iters}, err={err64:.3e}")
 
+    sched = None
+    if prec != gcp.Precision.FP64:
+        log(f"[bench] schedule {prec.name} -> FP64 below |Tr(D Dbar)| = 1e-2, stop at 1e-9")
+        with gcp.Context(M, precision=prec, late_precision="fp64", switch_ddbar=1e-2,
+                         tol_ddbar=1e-9, max_iter=100, fold_every=args.fold_every) as sctx:
+            Ds = torch.empty((M, M), dtype=torch.float64, device="cuda")
+            for rep in range(2):   # warm-up + timed
+                sctx.init(H, N, w.emin, w.emax)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, rs = sctx.purify(out=Ds)
+                torch.cuda.synchronize()
+                ts = time.perf_counter() - t0
+        Dsh = Ds.cpu().numpy()
+        sched = {"late_precision": "fp64", "switch_ddbar": 1e-2, "tol_ddbar": 1e-9,
+                 "time_to_solution_ms": ts * 1e3, "iters": rs.iters, "status": rs.status,
+                 "err": float(np.linalg.norm(Dsh - D_ref) / math.sqrt(M)), "idem": rs.idem,
+                 "trace_err": abs(float(np.trace(Dsh)) - N)}
+        del Ds, Dsh
+
     log("[bench] FP64 acceptance checks of the mixed result (gcp_verify)")
     with gcp.Context(M, precision=prec, tol_ddbar=tol_for(prec), max_iter=100,
                      fold_every=args.fold_every) as vctx:
@@ -318,6 +352,7 @@ def main() -> int:
         "speedup_vs_fp64": (fp64["time_to_solution_ms"] / (t_mixed * 1e3)) if fp64 else None,
         "backward": bwd,
         "verify": verify,
+        "schedule": sched,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": (f"k_gemm16<{prec.name}>" if gcp.MFMA_DTYPE[prec] in ("fp16", "bf16")

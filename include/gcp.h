@@ -91,6 +91,16 @@ typedef struct {
                               M x M matrix of the adjoint's type per update (default 0) */
     int32_t bwd_precision; /* arithmetic of gcp_backward: GCP_FP64 (default) or GCP_FP32
                               (FP32 MFMA and storage; kappa and the traces stay FP64) */
+    int32_t late_precision; /* precision schedule: -1 (default) = none; otherwise the
+                               encoding of every product once |Tr(D Dbar)| <= switch_ddbar.
+                               The switch re-encodes D and D^2 (the FP64 diagonal is
+                               kept), so Tr D stays exact.  Rounding already made in the
+                               occupied-virtual block is not undone by a later, more
+                               precise encoding: a late FP64 phase makes the result
+                               idempotent to FP64 level and lets it reach tolerances
+                               below the early encoding's rounding floor. */
+    int32_t pad;
+    double switch_ddbar;   /* see late_precision (default 0) */
 } gcp_options;
 
 typedef struct {

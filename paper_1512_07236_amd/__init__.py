@@ -67,7 +67,9 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("tol_ddbar", ctypes.c_double), ("tol_idem", ctypes.c_double),
                 ("fold_every", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("keep_iterates", ctypes.c_int32), ("bwd_precision", ctypes.c_int32)]
+                ("keep_iterates", ctypes.c_int32), ("bwd_precision", ctypes.c_int32),
+                ("late_precision", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("switch_ddbar", ctypes.c_double)]
 
 
 class CResult(ctypes.Structure):
@@ -168,7 +170,8 @@ class Context:
 
     def __init__(self, M: int, precision="fp64", max_iter: int = 100, tol_ddbar: float = 1e-6,
                  tol_idem: float = 0.0, fold_every: int = 0, profile: bool = False,
-                 keep_iterates: bool = False, bwd_precision="fp64", stream=None):
+                 keep_iterates: bool = False, bwd_precision="fp64", late_precision=None,
+                 switch_ddbar: float = 0.0, stream=None):
         L = load_library()
         self._L = L
         self.M = int(M)
@@ -182,6 +185,8 @@ class Context:
         o.profile = 1 if profile else 0
         o.keep_iterates = 1 if keep_iterates else 0
         o.bwd_precision = int(Precision.parse(bwd_precision))
+        o.late_precision = -1 if late_precision is None else int(Precision.parse(late_precision))
+        o.switch_ddbar = float(switch_ddbar)
         self.options = o
         self._stream = stream
         h = ctypes.c_void_p()

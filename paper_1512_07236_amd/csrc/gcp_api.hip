@@ -64,9 +64,18 @@ struct gcp_ctx {
   double *s2 = nullptr, *d3 = nullptr;
   double *part = nullptr, *tpart = nullptr, *bpart = nullptr;
   double *hvec = nullptr;   // 3 Mp scratch for H statistics
-  // K-split tail of the 16-bit product kernel (see k_gemm16)
-  int g16_full = 0, g16_split = 1;
-  float *g16_ws = nullptr;
+  // launch configuration per encoding: [0] the main precision, [1] the late
+  // precision of a schedule (unused without one)
+  struct PrecCfg {
+    int prec = GCP_FP64;
+    int ntpart = 0;   // tile partial sums the reduction adds
+    int fold = 1;     // fold period of the 16-bit kernel (K stages)
+    int nfull = 0;    // 16-bit kernel: pairs computed whole ...
+    int nsplit = 1;   // ... and K splits of each remaining pair
+  } pc[2];
+  int nprec = 1;
+  void *Xc = nullptr;       // conversion target of a precision switch
+  float *g16_ws = nullptr;  // K-split partial tiles (see k_gemm16)
   unsigned *g16_cnt = nullptr;
   unsigned *counter = nullptr;
   Scalars *sc = nullptr;    // device
@@ -104,9 +113,17 @@ struct gcp_ctx {
     }                                                                              \
   } while (0)
 
+static size_t plane_bytes_of(const gcp_ctx *c, int prec) {
+  return (size_t)plane_count(prec) * (size_t)c->Mp * (size_t)c->Mp * (size_t)elem_size(prec);
+}
+// Operand buffers hold any encoding the context's schedule uses.
 static size_t plane_bytes(const gcp_ctx *c) {
-  return (size_t)plane_count(c->opt.precision) * (size_t)c->Mp * (size_t)c->Mp *
-         (size_t)elem_size(c->opt.precision);
+  size_t b = 0;
+  for (int k = 0; k < c->nprec; ++k) {
+    const size_t x = plane_bytes_of(c, c->pc[k].prec);
+    if (x > b) b = x;
+  }
+  return b;
 }
 
 static void free_all(gcp_ctx *c) {
@@ -116,7 +133,7 @@ static void free_all(gcp_ctx *c) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   void *bptrs[] = {c->bG[0], c->bG[1], c->bX2, c->bAT, c->bCT, c->btpart, c->bvec, c->g16_ws,
-                   c->g16_cnt, c->vD, c->vH, c->vHD, c->vaux};
+                   c->g16_cnt, c->vD, c->vH, c->vHD, c->vaux, c->Xc};
   for (void *p : bptrs)
     if (p) (void)hipFree(p);
   for (void *p : c->slots)
@@ -125,6 +142,46 @@ static void free_all(gcp_ctx *c) {
   if (c->sc_host) (void)hipHostFree(c->sc_host);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   c->events.clear();
+}
+
+// Launch configuration of encoding pc[k].prec: tile partial count, fold
+// period and the K-split tail of the 16-bit kernel.
+static void PrecCfgInit(gcp_ctx *c, int k) {
+  gcp_ctx::PrecCfg &q = c->pc[k];
+  const int prec = q.prec;
+  const int np = plane_count(prec);
+  q.ntpart = elem_size(prec) == 2 ? 2 * pair_count(c->nt) : c->ntiles;
+  // fold period of the 16-bit kernel, in K stages: sqrt(stages / products
+  // per stage) unless given.  One- and two-plane encodings stage 64 halves
+  // per row (64 K values of one plane, or 32 of both); three planes 32 K.
+  const int nk = np <= 2 ? (int)(c->Mp * np / 64) : (int)(c->Mp / 32);
+  const double per_stage = np == 1 ? 2.0 : (double)products(prec);
+  int f = c->opt.fold_every;
+  if (f <= 0) f = (int)std::lround(std::sqrt((double)nk / per_stage));
+  q.fold = f < 1 ? 1 : f;
+  q.nfull = pair_count(c->nt);
+  q.nsplit = 1;
+  if (elem_size(prec) != 2) return;
+  // Pairs are equal units of work, one resident block per CU: the last
+  // partial round of np % CUs pairs would leave most CUs idle, so each of
+  // those pairs is split along K over up to min(CUs / tail, 4) blocks (at
+  // least 8 K stages each) and finished by the last of its splits.  At
+  // M = 8192 (32 tail pairs) 4 splits measured 2.06 ms per product against
+  // 2.24 unsplit and 2.14 with 8 (each split re-pays the pipeline fill and
+  // writes a 128 KB partial).
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  const int npairs = pair_count(c->nt);
+  const int tail = npairs % cus;
+  int S = tail > 0 ? cus / tail : 1;
+  if (S > nk / 8) S = nk / 8;
+  if (S > 4) S = 4;
+  if (tail > 0 && S >= 2) {
+    q.nfull = npairs - tail;
+    q.nsplit = S;
+  }
 }
 
 extern "C" int gcp_options_default(gcp_options *opt) {
@@ -138,6 +195,8 @@ extern "C" int gcp_options_default(gcp_options *opt) {
   opt->profile = 0;
   opt->keep_iterates = 0;
   opt->bwd_precision = GCP_FP64;
+  opt->late_precision = -1;
+  opt->switch_ddbar = 0.0;
   return GCP_OK;
 }
 
@@ -167,6 +226,10 @@ extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void
     g_create_error = "gcp_create: keep_iterates must be 0 or 1 and bwd_precision FP64 or FP32";
     return GCP_ERR_INVALID_ARG;
   }
+  if (o.late_precision < -1 || o.late_precision > GCP_BF16X6 || !(o.switch_ddbar >= 0.0)) {
+    g_create_error = "gcp_create: late_precision must be -1 or a precision, switch_ddbar >= 0";
+    return GCP_ERR_INVALID_ARG;
+  }
   gcp_ctx *c = new (std::nothrow) gcp_ctx();
   if (!c) {
     g_create_error = "gcp_create: out of host memory";
@@ -176,13 +239,23 @@ extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void
   c->Mp = (M + 255) / 256 * 256;   // whole pairs of 128-wide tiles
   c->nt = (int)(c->Mp / 128);
   c->ntiles = c->nt * (c->nt + 1) / 2;
-  // tile partial sums: one per upper tile (FP64/FP32 kernel) or two per
-  // tile pair (16-bit kernel, zero for the half of a pair below the diagonal)
-  c->ntpart = elem_size(o.precision) == 2 ? 2 * pair_count(c->nt) : c->ntiles;
   c->nred = (int)((c->Mp + 255) / 256);
   c->opt = o;
   c->stream = (hipStream_t)stream;
   (void)hipGetDevice(&c->device);
+  c->pc[0].prec = o.precision;
+  c->nprec = 1;
+  if (o.late_precision >= 0 && o.late_precision != o.precision) {
+    c->pc[1].prec = o.late_precision;
+    c->nprec = 2;
+  }
+  // tile partial sums: one per upper tile (FP64/FP32 kernel) or two per
+  // tile pair (16-bit kernel, zero for the half of a pair below the diagonal)
+  c->ntpart = 0;
+  for (int k = 0; k < c->nprec; ++k) {
+    PrecCfgInit(c, k);
+    if (c->pc[k].ntpart > c->ntpart) c->ntpart = c->pc[k].ntpart;
+  }
 
   const size_t Mp = (size_t)c->Mp;
   const size_t vec = Mp * sizeof(double);
@@ -217,35 +290,20 @@ extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void
   alloc((void **)&c->counter, sizeof(unsigned));
   alloc((void **)&c->sc, sizeof(Scalars));
   alloc((void **)&c->hist, (size_t)(o.max_iter + 1) * GCP_HIST_COLS * sizeof(double));
-  if (elem_size(o.precision) == 2) {
-    // Pairs are equal units of work, one resident block per CU: the last
-    // partial round of np % CUs pairs would leave most CUs idle, so each of
-    // those pairs is split along K over up to min(CUs / tail, 4) blocks (at
-    // least 8 K stages each) and finished by the last of its splits.  At
-    // M = 8192 (32 tail pairs) 4 splits measured 2.06 ms per product against
-    // 2.24 unsplit and 2.14 with 8 (each split re-pays the pipeline fill and
-    // writes a 128 KB partial).
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-    const int np = pair_count(c->nt);
-    const int npl = plane_count(o.precision);
-    const int nk = npl <= 2 ? (int)(c->Mp * npl / 64) : (int)(c->Mp / 32);
-    const int tail = np % cus;
-    int S = tail > 0 ? cus / tail : 1;
-    if (S > nk / 8) S = nk / 8;
-    if (S > 4) S = 4;
-    if (tail == 0 || S < 2) {
-      c->g16_full = np;
-      c->g16_split = 1;
-    } else {
-      c->g16_full = np - tail;
-      c->g16_split = S;
-      alloc((void **)&c->g16_ws, (size_t)tail * S * 512 * 64 * sizeof(float));
+  {
+    // K-split tail of the 16-bit kernel: partial tiles for the largest split
+    int tail = 0, smax = 1;
+    for (int k = 0; k < c->nprec; ++k)
+      if (c->pc[k].nsplit > 1) {
+        tail = pair_count(c->nt) - c->pc[k].nfull;
+        if (c->pc[k].nsplit > smax) smax = c->pc[k].nsplit;
+      }
+    if (tail > 0) {
+      alloc((void **)&c->g16_ws, (size_t)tail * smax * 512 * 64 * sizeof(float));
       alloc((void **)&c->g16_cnt, (size_t)tail * sizeof(unsigned));
     }
   }
+  if (c->nprec > 1) alloc(&c->Xc, pb);
   if (o.keep_iterates) {
     const size_t bb = Mp * Mp * (size_t)elem_size(o.bwd_precision);
     alloc(&c->bG[0], bb);
@@ -264,8 +322,10 @@ extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void
     g_create_error = "gcp_create: device allocation failed";
     return GCP_ERR_NO_MEMORY;
   }
-  if ((c->g16_cnt && hipMemsetAsync(c->g16_cnt, 0,
-                                     (size_t)(pair_count(c->nt) - c->g16_full) * sizeof(unsigned),
+  int ntail = 0;
+  for (int k = 0; k < c->nprec; ++k)
+    if (c->pc[k].nsplit > 1) ntail = pair_count(c->nt) - c->pc[k].nfull;
+  if ((c->g16_cnt && hipMemsetAsync(c->g16_cnt, 0, (size_t)ntail * sizeof(unsigned),
                                      c->stream) != hipSuccess) ||
       hipMemsetAsync(c->counter, 0, sizeof(unsigned), c->stream) != hipSuccess ||
       hipMemsetAsync(c->s2, 0, vec, c->stream) != hipSuccess ||
@@ -291,7 +351,7 @@ extern "C" const char *gcp_last_error(const gcp_ctx *c) {
 }
 
 static int reduce(gcp_ctx *c, const double *part, int nslots, int mode, double *out,
-                  const double *extra, const double *tpart, int iter) {
+                  const double *extra, const double *tpart, int ntp, int iter) {
   RedArgs a{};
   a.part = part;
   a.nslots = nslots;
@@ -302,7 +362,7 @@ static int reduce(gcp_ctx *c, const double *part, int nslots, int mode, double *
   a.bpart = c->bpart;
   a.counter = c->counter;
   a.tpart = tpart;
-  a.ntiles = c->ntpart;
+  a.ntiles = ntp;
   a.iter = iter;
   a.max_iter = c->opt.max_iter;
   a.tol_ddbar = c->opt.tol_ddbar;
@@ -371,7 +431,7 @@ extern "C" int gcp_init(gcp_ctx *c, const double *H, int64_t ldh, int64_t N, dou
   a.rD = c->rD0;
   a.part = c->part;
   HIPCHK(c, launch_init(c->opt.precision, a, c->stream));
-  int st = reduce(c, c->part, (int)(c->Mp / 64), 0, c->d20, c->dg0, nullptr, 0);
+  int st = reduce(c, c->part, (int)(c->Mp / 64), 0, c->d20, c->dg0, nullptr, 0, 0);
   if (st != GCP_OK) return st;
   HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -394,7 +454,7 @@ extern "C" int gcp_get_init_scalars(const gcp_ctx *c, double *mu, double *beta, 
 }
 
 // Keeps iterate D_n (forward planes Dp[k] plus its FP64 diagonal) as slot n.
-static int store_iterate(gcp_ctx *c, int n, int k) {
+static int store_iterate(gcp_ctx *c, int n, int k, int prec) {
   const size_t bytes = (size_t)c->Mp * (size_t)c->Mp * (size_t)elem_size(c->opt.bwd_precision);
   while ((int)c->slots.size() <= n) {
     void *p = nullptr;
@@ -404,7 +464,7 @@ static int store_iterate(gcp_ctx *c, int n, int k) {
     }
     c->slots.push_back(p);
   }
-  HIPCHK(c, launch_bwd_store(c->opt.precision, c->opt.bwd_precision, c->Dp[k], c->dg[k], c->Mp,
+  HIPCHK(c, launch_bwd_store(prec, c->opt.bwd_precision, c->Dp[k], c->dg[k], c->Mp,
                              c->slots[n], c->stream));
   return GCP_OK;
 }
@@ -420,7 +480,8 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
     return GCP_ERR_INVALID_ARG;
   }
   const auto t_start = std::chrono::steady_clock::now();
-  const int prec = c->opt.precision;
+  int pi = 0;                         // index of the current encoding in c->pc
+  int prec = c->pc[0].prec;
   const size_t vec = (size_t)c->Mp * sizeof(double);
   const int64_t PS = c->Mp * c->Mp;
   const int max_iter = c->opt.max_iter;
@@ -440,7 +501,7 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
   const bool keep = c->opt.keep_iterates != 0;
   c->bwd_p = -1;
   if (keep) {
-    const int st = store_iterate(c, 0, 0);
+    const int st = store_iterate(c, 0, 0, prec);
     if (st != GCP_OK) return st;
   }
 
@@ -454,31 +515,24 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
     }
   }
   int nlaunch = 0;
-  auto gemm = [&](GemmArgs &g) -> int {
+  double mfma_flops = 0.0;
+  GemmArgs g{};
+  auto gemm = [&](GemmArgs &ga) -> int {
+    const gcp_ctx::PrecCfg &q = c->pc[pi];
+    ga.fold = q.fold;
+    ga.nfull = q.nfull;
+    ga.nsplit = q.nsplit;
     if (prof) HIPCHK(c, hipEventRecord(c->events[2 * nlaunch], c->stream));
-    HIPCHK(c, launch_gemm(prec, g, c->stream));
+    HIPCHK(c, launch_gemm(prec, ga, c->stream));
     if (prof) HIPCHK(c, hipEventRecord(c->events[2 * nlaunch + 1], c->stream));
     ++nlaunch;
+    mfma_flops += (double)c->ntiles * 2.0 * 128.0 * 128.0 * (double)c->Mp * (double)products(prec);
     return GCP_OK;
   };
 
-  GemmArgs g{};
   g.Mp = c->Mp;
   g.pstride = PS;
   g.nt = c->nt;
-  // fold period of the 16-bit kernel, in K stages: sqrt(stages / products
-  // per stage) unless given.  One- and two-plane encodings stage 64 halves
-  // per row (64 K values of one plane, or 32 of both); three planes 32 K.
-  {
-    const int np = plane_count(prec);
-    const double stages = np <= 2 ? (double)(c->Mp * np / 64) : (double)(c->Mp / 32);
-    const double per_stage = np == 1 ? 2.0 : (double)products(prec);
-    int f = c->opt.fold_every;
-    if (f <= 0) f = (int)std::lround(std::sqrt(stages / per_stage));
-    g.fold = f < 1 ? 1 : f;
-  }
-  g.nfull = c->g16_full;
-  g.nsplit = c->g16_split;
   g.ws = c->g16_ws;
   g.cnt = c->g16_cnt;
   g.part = c->part;
@@ -500,14 +554,27 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
     g.d2 = c->d2[k];
     int st = gemm(g);
     if (st != GCP_OK) return st;
-    st = reduce(c, c->part, c->nt, 1, c->d3, nullptr, c->tpart, n);
+    st = reduce(c, c->part, c->nt, 1, c->d3, nullptr, c->tpart, c->pc[pi].ntpart, n);
     if (st != GCP_OK) return st;
     HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     status = c->sc_host->status;
     if (status != 0) break;
+    if (pi == 0 && c->nprec > 1 &&
+        std::fabs(c->sc_host->t1 - c->sc_host->t2) <= c->opt.switch_ddbar) {
+      // precision schedule: re-encode D_n and X2 = D_n^2 for the rest of the
+      // solve; the FP64 diagonals (dg, d2, d3) and c_n are unchanged, the
+      // residuals of the new encoding replace rD and s2
+      const int pn = c->pc[1].prec;
+      HIPCHK(c, launch_convert(prec, pn, c->Dp[k], c->dg[k], c->Xc, c->rD[k], c->Mp, c->stream));
+      std::swap(c->Dp[k], c->Xc);
+      HIPCHK(c, launch_convert(prec, pn, c->X2p, c->d2[k], c->Xc, c->s2, c->Mp, c->stream));
+      std::swap(c->X2p, c->Xc);
+      pi = 1;
+      prec = pn;
+    }
     if (keep && n > 0) {
-      st = store_iterate(c, n, k);
+      st = store_iterate(c, n, k, prec);
       if (st != GCP_OK) return st;
     }
     // K2: D_{n+1} = (1 - 2c) D + (2 + 2c) X2 - 2 X2 D
@@ -519,7 +586,7 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
     g.rD_new = c->rD[1 - k];
     st = gemm(g);
     if (st != GCP_OK) return st;
-    st = reduce(c, c->part, c->nt, 2, c->d2[1 - k], c->dg[1 - k], c->tpart, n);
+    st = reduce(c, c->part, c->nt, 2, c->d2[1 - k], c->dg[1 - k], c->tpart, c->pc[pi].ntpart, n);
     if (st != GCP_OK) return st;
     c->cur = 1 - k;
   }
@@ -558,8 +625,7 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
     res->gemm_launches = nlaunch;
     const double Md = (double)c->M;
     res->gemm_flops = (double)nlaunch * Md * Md * (Md + 1.0);
-    res->mfma_flops = (double)nlaunch * (double)c->ntiles * 2.0 * 128.0 * 128.0 *
-                      (double)c->Mp * (double)products(prec);
+    res->mfma_flops = mfma_flops;
     double ms = 0.0;
     if (prof) {
       for (int k = 0; k < nlaunch; ++k) {

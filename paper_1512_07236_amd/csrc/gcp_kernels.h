@@ -136,6 +136,10 @@ int pair_count(int nt);
 int gemm16_blocks(const GemmArgs &g);
 hipError_t launch_init(int prec, const InitArgs &a, hipStream_t st);
 hipError_t launch_output(int prec, const OutArgs &a, hipStream_t st);
+// Re-encode an Mp x Mp iterate from encoding pa to pb (exact FP64 diagonal
+// from diag; the new diagonal residuals go to resid).
+hipError_t launch_convert(int pa, int pb, const void *in, const double *diag, void *out,
+                          double *resid, int64_t Mp, hipStream_t st);
 hipError_t launch_reduce(const RedArgs &a, hipStream_t st);
 hipError_t launch_hstats(const double *H, int64_t ldh, int64_t M, double *lo, double *hi,
                          double *hd, double *out, hipStream_t st);

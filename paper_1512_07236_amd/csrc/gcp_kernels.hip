@@ -882,6 +882,68 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a) {
     ((float *)a.D)[i * a.ldd + j] = (float)x;
 }
 
+// -------------------------------------------------- encoding conversion
+// Re-encodes an iterate from encoding PA to PB (precision schedule): the
+// off-diagonal master values dec_A(planes) are encoded in B; the diagonal
+// is the exact FP64 vector diag, encoded in B with its residual
+// diag - dec_B(enc_B(diag)) written to resid.
+template <int P>
+__device__ __forceinline__ double dec_at(const void *b, int64_t i, int64_t j, int64_t Mp) {
+  using E = Enc<P>;
+  typename E::T p[E::NP];
+#pragma unroll
+  for (int q = 0; q < E::NP; ++q) p[q] = ((const typename E::T *)b)[eoff<P>(i, j, q, Mp)];
+  return E::dec(p);
+}
+template <int P>
+__device__ __forceinline__ double enc_at(void *b, int64_t i, int64_t j, int64_t Mp, double x) {
+  using E = Enc<P>;
+  typename E::T p[E::NP];
+  E::enc(x, p);
+#pragma unroll
+  for (int q = 0; q < E::NP; ++q) ((typename E::T *)b)[eoff<P>(i, j, q, Mp)] = p[q];
+  return E::dec(p);
+}
+
+__device__ __forceinline__ double enc_any(int pb, void *out, int64_t i, int64_t j, int64_t Mp,
+                                            double x) {
+  switch (pb) {
+    case GCP_FP64: return enc_at<GCP_FP64>(out, i, j, Mp, x);
+    case GCP_FP32: return enc_at<GCP_FP32>(out, i, j, Mp, x);
+    case GCP_BF16: return enc_at<GCP_BF16>(out, i, j, Mp, x);
+    case GCP_FP16: return enc_at<GCP_FP16>(out, i, j, Mp, x);
+    case GCP_BF16X3: return enc_at<GCP_BF16X3>(out, i, j, Mp, x);
+    case GCP_FP16X3: return enc_at<GCP_FP16X3>(out, i, j, Mp, x);
+    default: return enc_at<GCP_BF16X6>(out, i, j, Mp, x);
+  }
+}
+
+template <int PA>
+__global__ __launch_bounds__(256) void k_convert(int pb, const void *in, const double *diag, void *out,
+                                                 double *resid, int64_t Mp) {
+  const int64_t i = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const double x = (i == j) ? diag[i] : dec_at<PA>(in, i, j, Mp);
+  const double xe = enc_any(pb, out, i, j, Mp, x);
+  if (i == j) resid[i] = x - xe;
+}
+
+hipError_t launch_convert(int pa, int pb, const void *in, const double *diag, void *out,
+                          double *resid, int64_t Mp, hipStream_t st) {
+  const dim3 grid((unsigned)(Mp / 256), (unsigned)Mp);
+  switch (pa) {
+    case GCP_FP64: k_convert<GCP_FP64><<<grid, 256, 0, st>>>(pb, in, diag, out, resid, Mp); break;
+    case GCP_FP32: k_convert<GCP_FP32><<<grid, 256, 0, st>>>(pb, in, diag, out, resid, Mp); break;
+    case GCP_BF16: k_convert<GCP_BF16><<<grid, 256, 0, st>>>(pb, in, diag, out, resid, Mp); break;
+    case GCP_FP16: k_convert<GCP_FP16><<<grid, 256, 0, st>>>(pb, in, diag, out, resid, Mp); break;
+    case GCP_BF16X3: k_convert<GCP_BF16X3><<<grid, 256, 0, st>>>(pb, in, diag, out, resid, Mp); break;
+    case GCP_FP16X3: k_convert<GCP_FP16X3><<<grid, 256, 0, st>>>(pb, in, diag, out, resid, Mp); break;
+    case GCP_BF16X6: k_convert<GCP_BF16X6><<<grid, 256, 0, st>>>(pb, in, diag, out, resid, Mp); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- dispatch
 template <int P>
 static hipError_t launch_gemm_p(const GemmArgs &g, int ntiles, hipStream_t st) {

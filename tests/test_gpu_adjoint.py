@@ -277,3 +277,17 @@ def test_full_size_spectral_8192_against_daleckii_krein(precision, bwd, tol_ddba
         f"({bres.gemm_flops / bres.ms_total / 1e9:.1f} TFLOP/s algorithmic)")
     assert np.array_equal(dH, dH.T)
     assert err <= err_tol
+
+
+def test_adjoint_through_a_precision_switch():
+    """FP16X3 then FP64 (switch below Tr(D Dbar) = 1e-3): the kept iterates
+    change encoding mid-run; the FP64 adjoint still matches the oracle's."""
+    w = workloads.spectral(384, 150, 0.1, 34)
+    Gp = workloads.sym_gaussian(384, 234)
+    dH, res, _ = gpu_grad(w, Gp, precision="fp16x3", late_precision="fp64", switch_ddbar=1e-3,
+                          tol_ddbar=1e-9)
+    assert res.status == gcp.OK
+    ref = grad.adjoint(w.H, w.N, w.emin, w.emax, res.iters, Gp)
+    err = rel_max(dH, ref)
+    log(f"  p={res.iters} err={err:.3e}")
+    assert err <= 1e-3

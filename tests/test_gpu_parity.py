@@ -276,3 +276,56 @@ def test_full_size_spectral_8192(config3, precision, tol_ddbar, err_tol):
     ctol, cnum = (1e-11, 1e-12) if precision == "fp64" else (1e-4, 1e-5)
     assert np.all(np.abs(res.col("c")[:n] - s["c"][:n]) <= ctol + cnum / np.abs(ddbar))
     assert abs(res.iters - s["iters"]) <= (0 if precision == "fp64" else 1)
+
+
+# ------------------------------------------------------- precision schedule
+
+def _ctx_run(w, **opts):
+    with gcp.Context(w.M, **opts) as ctx:
+        ctx.init(to_gpu(w.H), w.N, w.emin, w.emax)
+        D, res = ctx.purify()
+        torch.cuda.synchronize()
+        return D.cpu().numpy(), res
+
+
+def test_schedule_never_triggered_is_bitwise_the_single_precision_run():
+    w = workloads.spectral(384, 150, 0.1, 50)
+    D1, r1 = _ctx_run(w, precision="fp16x3", tol_ddbar=1e-6)
+    D2, r2 = _ctx_run(w, precision="fp16x3", late_precision="fp64", switch_ddbar=0.0,
+                      tol_ddbar=1e-6)
+    assert r1.iters == r2.iters and np.array_equal(D1, D2)
+
+
+def test_schedule_from_the_start_matches_the_late_precision_run():
+    """FP64 -> FP16X3 at n = 0: only the first D^2 is FP64, so the run is the
+    FP16X3 run up to FP16X3 rounding."""
+    w = workloads.spectral(384, 150, 0.1, 51)
+    ref = oracle.projector_from_spectrum(w.Q, w.lam, w.N)
+    D1, r1 = _ctx_run(w, precision="fp16x3", tol_ddbar=1e-6)
+    D2, r2 = _ctx_run(w, precision="fp64", late_precision="fp16x3", switch_ddbar=1e30,
+                      tol_ddbar=1e-6)
+    assert abs(r1.iters - r2.iters) <= 1
+    assert rel_err(D2, ref) < ERR_TOL["fp16x3"]
+    assert np.abs(r2.col("t1") - w.N).max() < 1e-10
+
+
+@pytest.mark.parametrize("early,late,switch,err_lo,err_hi", [("fp16x3", "fp64", 1e-3, 0.0, 1e-6),
+                                                             ("bf16", "fp16x3", 1e-1, 1e-4, 3e-2)])
+def test_schedule_switch(early, late, switch, err_lo, err_hi):
+    """Trace exact through the switch, convergence below the early encoding's
+    rounding floor when the late one is FP64, and the early phase's error kept
+    (rounding in the occupied-virtual block is not undone later).  The switch
+    point lies above the early encoding's floor of Tr(D Dbar) (TOL_DDBAR)."""
+    M, N = 520, 200
+    w = workloads.spectral(M, N, 0.1, 52)
+    ref = oracle.projector_from_spectrum(w.Q, w.lam, w.N)
+    tol = 1e-11 if late == "fp64" else 1e-5
+    D, res = _ctx_run(w, precision=early, late_precision=late, switch_ddbar=switch,
+                      tol_ddbar=tol, max_iter=60)
+    err = rel_err(D, ref)
+    log(f"  {early}->{late}: iters={res.iters} err={err:.3e} idem={res.idem:.2e}")
+    assert res.status == gcp.OK
+    assert np.abs(res.col("t1") - w.N).max() < 1e-10
+    assert err_lo <= err < err_hi
+    if late == "fp64":
+        assert res.idem < 1e-9
