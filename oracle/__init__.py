@@ -36,6 +36,8 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 OK, NOT_CONVERGED, BREAKDOWN, INVALID = 0, 1, 2, -1
 HIST_COLS = 9
 HIST_FIELDS = ("n", "t1", "t2", "t3", "c", "omega", "gamma", "lagrangian", "step")
+METHODS = {"hpcp": 0, "pmcp": 1}           # eq. (hpcp3) / eqs. (pm1a),(pm1b)
+INITS = {"pmcp": 0, "hp": 1, "search": 2}  # eq. (pmcpguess) / eq. (hpcpguess) / its alpha search
 
 
 def build(force: bool = True) -> str:
@@ -66,9 +68,17 @@ def lib():
         L.oracle_initial_guess.restype = cint
         L.oracle_purify_from.argtypes = [i64, i64, P, dbl, dbl, cint, P, ctypes.POINTER(cint)]
         L.oracle_purify_from.restype = cint
+        L.oracle_purify_from_m.argtypes = [i64, i64, P, cint, dbl, dbl, cint, P,
+                                           ctypes.POINTER(cint)]
+        L.oracle_purify_from_m.restype = cint
         L.oracle_purify.argtypes = [i64, i64, P, dbl, dbl, dbl, dbl, cint, P, P,
                                     ctypes.POINTER(cint), P]
         L.oracle_purify.restype = cint
+        L.oracle_purify_ex.argtypes = [i64, i64, P, dbl, dbl, cint, cint, dbl, dbl, dbl, dbl,
+                                       cint, P, P, ctypes.POINTER(cint), P]
+        L.oracle_purify_ex.restype = cint
+        L.oracle_initial_guess_hp.argtypes = [i64, i64, P, dbl, dbl, cint, dbl, dbl, P, P]
+        L.oracle_initial_guess_hp.restype = cint
         L.oracle_jacobi_eigh.argtypes = [i64, P, P, P, dbl, cint]
         L.oracle_jacobi_eigh.restype = cint
         L.oracle_projector.argtypes = [i64, i64, P, P]
@@ -153,15 +163,54 @@ def purify(H: np.ndarray, N: int, emin: float = float("nan"), emax: float = floa
     return Result(D, st, n, hist[: n + 1].copy(), *scal)
 
 
+def purify_ex(H: np.ndarray, N: int, emin: float = float("nan"), emax: float = float("nan"),
+              method: str = "hpcp", init: str = "pmcp", alpha: float = 0.5,
+              delta: float = 2.0 / 3.0, tol_ddbar: float = 1e-6, tol_idem: float = 0.0,
+              max_iter: int = 100) -> Result:
+    """purify with a choice of recursion (HPCP eq. (hpcp3) or PMCP eqs.
+    (pm1a)/(pm1b)) and initial guess (PMCP guess, hole-particle mix with alpha,
+    or the alpha search).  Result.alpha is the alpha used (1 = PMCP guess)."""
+    H = _f64(H)
+    M = H.shape[0]
+    D = np.empty((M, M))
+    hist = np.full((max_iter + 1, HIST_COLS), np.nan)
+    iters = ctypes.c_int()
+    scal = np.empty(5)
+    st = lib().oracle_purify_ex(M, N, _p(H), emin, emax, METHODS[method], INITS[init], alpha,
+                                delta, tol_ddbar, tol_idem, max_iter, _p(D), _p(hist),
+                                ctypes.byref(iters), _p(scal))
+    if st == INVALID:
+        raise ValueError("invalid purification input")
+    n = iters.value
+    r = Result(D, st, n, hist[: n + 1].copy(), *scal[:4])
+    r.alpha = float(scal[4])
+    return r
+
+
+def initial_guess_hp(H: np.ndarray, N: int, emin: float, emax: float, init: str = "hp",
+                     alpha: float = 0.5, delta: float = 2.0 / 3.0):
+    """Hole-particle guess of eq. (hpcpguess) as a matrix: (D0+, mu, slope, alpha)."""
+    H = _f64(H)
+    M = H.shape[0]
+    D0 = np.empty((M, M))
+    scal = np.empty(3)
+    st = lib().oracle_initial_guess_hp(M, N, _p(H), emin, emax, INITS[init], alpha, delta,
+                                       _p(D0), _p(scal))
+    if st != OK:
+        raise ValueError("invalid purification input")
+    return D0, float(scal[0]), float(scal[1]), float(scal[2])
+
+
 def purify_from(D0: np.ndarray, N: int, tol_ddbar: float = 1e-6, tol_idem: float = 0.0,
-                max_iter: int = 100) -> Result:
-    """HPCP recursion from a given symmetric D0 (copied)."""
+                max_iter: int = 100, method: str = "hpcp") -> Result:
+    """The recursion (HPCP, or PMCP with method="pmcp") from a given symmetric
+    D0 (copied)."""
     D = _f64(D0).copy()
     M = D.shape[0]
     hist = np.full((max_iter + 1, HIST_COLS), np.nan)
     iters = ctypes.c_int()
-    st = lib().oracle_purify_from(M, N, _p(D), tol_ddbar, tol_idem, max_iter, _p(hist),
-                                  ctypes.byref(iters))
+    st = lib().oracle_purify_from_m(M, N, _p(D), METHODS[method], tol_ddbar, tol_idem, max_iter,
+                                    _p(hist), ctypes.byref(iters))
     n = iters.value
     return Result(D, st, n, hist[: n + 1].copy())
 
@@ -214,7 +263,9 @@ def verify_quantities(D: np.ndarray, H: np.ndarray) -> dict:
 
 
 def scalar_map(eps: np.ndarray, N: int, emin: float, emax: float, mu: Optional[float] = None,
-               tol_ddbar: float = 1e-6, tol_idem: float = 0.0, max_iter: int = 100):
+               tol_ddbar: float = 1e-6, tol_idem: float = 0.0, max_iter: int = 100,
+               method: str = "hpcp", init: str = "pmcp", alpha: float = 0.5,
+               delta: float = 2.0 / 3.0):
     """The recursion on eigenvalues (H with known spectrum eps).
 
     Every iterate is a polynomial in H, so D_n has the eigenvectors of H and
@@ -222,6 +273,12 @@ def scalar_map(eps: np.ndarray, N: int, emin: float, emax: float, mu: Optional[f
     eq. (hpcp3) to numbers: x <- x + 2 (x^2 (1-x) - c x (1-x)),
     c = sum x^2(1-x) / sum x(1-x).  Returns dict(status, iters, c, t1, t2, t3,
     omega, x) with per-iterate arrays; the same termination rule as ``purify``.
+
+    method "pmcp" maps by eqs. (pm1a)/(pm1b) instead; init "hp" / "search" use
+    the hole-particle guess of eq. (hpcpguess) with the given alpha or the
+    alpha of the search of eq. (hpcpguessalpha), on eigenvalues (the same
+    readings as the C oracle, including the fall-back to the PMCP guess when
+    c_0 is outside [0, 1]).
     """
     eps = np.asarray(eps, dtype=np.float64)
     M = eps.size
@@ -229,8 +286,43 @@ def scalar_map(eps: np.ndarray, N: int, emin: float, emax: float, mu: Optional[f
     if mu is None:
         mu = float(np.sum(eps)) / M
     beta = 0.0
+    alpha_used = 1.0
     if 0 < N < M:
-        beta = min(theta / (emax - mu), (1 - theta) / (mu - emin))
+        bt, bb = theta / (emax - mu), (1 - theta) / (mu - emin)
+        bmin, bmax = min(bt, bb), max(bt, bb)
+        beta = bmin
+        if init != "pmcp":
+            a = alpha
+            if init == "search":
+                if theta < 1 - delta:
+                    target = N - delta * N
+                elif theta > delta:
+                    target = N - delta * (M - N)
+                else:
+                    target = None
+                if target is None:
+                    a = 0.5
+                else:
+                    f = [float(np.sum((theta + (t * bmin + (1 - t) * bmax) * (mu - eps)) ** 2))
+                         for t in (0.0, 0.5, 1.0)]
+                    qa = 2 * f[2] - 4 * f[1] + 2 * f[0]
+                    qb = f[2] - f[0] - qa
+                    roots = np.roots([qa, qb, f[0] - target]) if qa != 0 else np.array([])
+                    roots = [r.real for r in roots if abs(r.imag) == 0]
+                    inside = [r for r in roots if 0.0 <= r <= 1.0]
+                    if inside:
+                        a = inside[0] if len(inside) == 1 else min(inside)
+                    elif roots:
+                        a = min(roots, key=lambda r: abs(r - 0.5))
+                    else:
+                        a = 1.0 if f[2] > target else 0.0
+                    a = min(1.0, max(0.0, a))
+            bhp = a * bmin + (1 - a) * bmax
+            x = theta + bhp * (mu - eps)
+            t1, t2, t3 = x.sum(), (x * x).sum(), (x ** 3).sum()
+            c0 = (t2 - t3) / (t1 - t2) if t1 > t2 else float("nan")
+            if 0.0 <= c0 <= 1.0:
+                beta, alpha_used = bhp, a
     x = theta + beta * (mu - eps)
     out = {k: [] for k in ("t1", "t2", "t3", "c", "omega")}
     status = NOT_CONVERGED
@@ -253,8 +345,13 @@ def scalar_map(eps: np.ndarray, N: int, emin: float, emax: float, mu: Optional[f
         if not (0.0 <= c <= 1.0):
             status = BREAKDOWN
             break
-        x = x + 2.0 * (x * x * (1 - x) - c * x * (1 - x))
+        if method == "hpcp":
+            x = x + 2.0 * (x * x * (1 - x) - c * x * (1 - x))
+        elif c <= 0.5:
+            x = ((1 - 2 * c) * x + (1 + c) * x * x - x ** 3) / (1 - c)
+        else:
+            x = ((1 + c) * x * x - x ** 3) / c
         n += 1
     res = {k: np.array(v) for k, v in out.items()}
-    res.update(status=status, iters=n, x=x, beta=beta, mu=mu)
+    res.update(status=status, iters=n, x=x, beta=beta, mu=mu, alpha=alpha_used)
     return res

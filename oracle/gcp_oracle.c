@@ -22,6 +22,15 @@
  *   eq. (mcw1b)       McWeeny functional Omega = Tr((D^2 - D)^2) = ||D^2 - D||_F^2
  *   eq. (mcw4b)       Lagrangian L = Omega - gamma (Tr(3D^2 - 2D^3) - N)
  *   eq. (mcwgama)     gamma = 1/3 - 2/3 c   (d = 0)
+ *   eqs. (pm1a),(pm1b) the Palser-Manolopoulos canonical purification (PMCP)
+ *                     of the appendix: D' = [(1-2c)D + (1+c)D^2 - D^3]/(1-c)
+ *                     for c <= 1/2, D' = [(1+c)D^2 - D^3]/c for c > 1/2, with
+ *                     the same c
+ *   eq. (hpcpguess)   hole-particle guess D0+ = alpha D0 + (1-alpha)(I - Dbar0),
+ *                     Dbar0 from eqs. (dmguess)+(pmcpguess) with
+ *                     beta1 = 1-theta, beta2 = -max(beta_tilde, beta_bar)
+ *   eq. (hpcpguessalpha) alpha searched in [0,1] so that Tr(D0+^2) hits a
+ *                     target (a quadratic in alpha), delta ~ 2/3
  *
  * Where the paper is silent this file takes these readings:
  *   - symmetry of iterates: after each update D <- (D + D^T)/2 (diagonal, and
@@ -33,6 +42,13 @@
  *   - c outside [0,1], or Tr(D Dbar) < -tol_ddbar, before the tolerance is met
  *     is a breakdown (the paper calls these runaway solutions); nothing is
  *     clamped;
+ *   - the alpha-search targets (the paper's condition is garbled): Tr D0+^2 =
+ *     N - delta N when theta < 1 - delta, N - delta (M - N) when theta > delta,
+ *     and alpha = 1/2 in between (each target is reachable only on its side);
+ *     a root outside [0,1] is clamped to [0,1];
+ *   - if a hole-particle guess gives Tr(D0+ Dbar0+) <= 0 or c_0 outside [0,1]
+ *     (the runaway the paper reports for the naive alpha = 1/2 at extreme
+ *     fillings), the solve falls back to alpha = 1, the PMCP guess;
  *   - the eigensolver used for the definition D = sum of the lowest-N
  *     eigenprojectors is cyclic Jacobi (Golub & Van Loan, symmetric Schur
  *     rotations), the textbook method, written out here.
@@ -142,6 +158,95 @@ int oracle_initial_guess(int64_t M, int64_t N, const double *H, double emin,
     return ORACLE_OK;
 }
 
+/* Hole-particle guess, eq. (hpcpguess): the particle guess D0 (beta =
+ * min), the hole guess Dbar0 = (1-theta) I - max(beta_tilde, beta_bar)
+ * (mu I - H), and D0+ = alpha D0 + (1 - alpha)(I - Dbar0), formed as matrices.
+ * mode 1: alpha as given.  mode 2: alpha from the search of eq.
+ * (hpcpguessalpha): Tr(D0+(alpha)^2) is a quadratic in alpha, evaluated at
+ * alpha = 0, 1/2, 1 and solved for the target (readings above).
+ * scal (may be NULL) receives mu, the effective slope
+ * alpha*beta_min + (1-alpha)*beta_max, and alpha. */
+static void hp_mix(int64_t M, const double *P, const double *Hb, double alpha, double *out)
+{
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = 0; j < M; ++j) {
+            const double id = (i == j) ? 1.0 : 0.0;
+            out[i * M + j] = alpha * P[i * M + j] + (1.0 - alpha) * (id - Hb[i * M + j]);
+        }
+}
+
+static double frob2(int64_t M, const double *A)
+{
+    double s = 0.0;
+    for (int64_t e = 0; e < M * M; ++e) s += A[e] * A[e];
+    return s;
+}
+
+int oracle_initial_guess_hp(int64_t M, int64_t N, const double *H, double emin,
+                            double emax, int mode, double alpha, double delta,
+                            double *D0, double *scal)
+{
+    if (M <= 0 || N < 0 || N > M || (mode != 1 && mode != 2)) return ORACLE_INVALID;
+    const double theta = (double)N / (double)M;
+    const double mu = trace(M, H) / (double)M;
+    if (N == 0 || N == M) {   /* beta = 0: D0 = theta I whatever alpha */
+        for (int64_t e = 0; e < M * M; ++e) D0[e] = 0.0;
+        for (int64_t i = 0; i < M; ++i) D0[i * M + i] = theta;
+        if (scal) { scal[0] = mu; scal[1] = 0.0; scal[2] = 1.0; }
+        return ORACLE_OK;
+    }
+    if (!(emin < mu && mu < emax)) return ORACLE_INVALID;
+    const double bt = theta / (emax - mu), bb = (1.0 - theta) / (mu - emin);
+    const double bmin = bt < bb ? bt : bb, bmax = bt < bb ? bb : bt;
+    double *P = (double *)malloc(sizeof(double) * M * M);
+    double *Hb = (double *)malloc(sizeof(double) * M * M);
+    if (!P || !Hb) { free(P); free(Hb); return ORACLE_INVALID; }
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = 0; j < M; ++j) {
+            const double g = (i == j ? mu : 0.0) - H[i * M + j];   /* (mu I - H)_ij */
+            P[i * M + j] = (i == j ? theta : 0.0) + bmin * g;
+            Hb[i * M + j] = (i == j ? 1.0 - theta : 0.0) - bmax * g;
+        }
+    if (mode == 2) {
+        double target = NAN;
+        if (theta < 1.0 - delta) target = (double)N - delta * (double)N;
+        else if (theta > delta) target = (double)N - delta * (double)(M - N);
+        if (isnan(target)) {
+            alpha = 0.5;
+        } else {
+            hp_mix(M, P, Hb, 0.0, D0);
+            const double f0 = frob2(M, D0);
+            hp_mix(M, P, Hb, 0.5, D0);
+            const double fh = frob2(M, D0);
+            hp_mix(M, P, Hb, 1.0, D0);
+            const double f1 = frob2(M, D0);
+            /* q(alpha) = qa alpha^2 + qb alpha + f0 */
+            const double qa = 2.0 * f1 - 4.0 * fh + 2.0 * f0;
+            const double qb = f1 - f0 - qa;
+            const double qc = f0 - target;
+            double a = NAN;
+            if (fabs(qa) > 0.0) {
+                const double disc = qb * qb - 4.0 * qa * qc;
+                if (disc >= 0.0) {
+                    const double r1 = (-qb - sqrt(disc)) / (2.0 * qa);
+                    const double r2 = (-qb + sqrt(disc)) / (2.0 * qa);
+                    /* Tr D0+^2 falls on [0,1] (the slope falls from beta_max
+                       to beta_min): the root there, else the nearer one */
+                    if (r1 >= 0.0 && r1 <= 1.0) a = r1;
+                    else if (r2 >= 0.0 && r2 <= 1.0) a = r2;
+                    else a = fabs(r1 - 0.5) < fabs(r2 - 0.5) ? r1 : r2;
+                }
+            }
+            if (isnan(a)) a = (f1 > target) ? 1.0 : 0.0;   /* no real root: the nearer end */
+            alpha = a < 0.0 ? 0.0 : (a > 1.0 ? 1.0 : a);
+        }
+    }
+    hp_mix(M, P, Hb, alpha, D0);
+    if (scal) { scal[0] = mu; scal[1] = alpha * bmin + (1.0 - alpha) * bmax; scal[2] = alpha; }
+    free(P); free(Hb);
+    return ORACLE_OK;
+}
+
 /* ------------------------------------------------------------------ */
 /* The recursion, eq. (hpcp3)                                           */
 /* ------------------------------------------------------------------ */
@@ -164,8 +269,8 @@ int oracle_initial_guess(int64_t M, int64_t N, const double *H, double emin,
  * *iters = number of updates applied.  Returns ORACLE_OK,
  * ORACLE_NOT_CONVERGED or ORACLE_BREAKDOWN.
  */
-int oracle_purify_from(int64_t M, int64_t N, double *D, double tol_ddbar,
-                       double tol_idem, int max_iter, double *hist, int *iters)
+int oracle_purify_from_m(int64_t M, int64_t N, double *D, int method, double tol_ddbar,
+                         double tol_idem, int max_iter, double *hist, int *iters)
 {
     const int64_t MM = M * M;
     double *X2 = (double *)malloc(sizeof(double) * MM);
@@ -221,11 +326,21 @@ int oracle_purify_from(int64_t M, int64_t N, double *D, double tol_ddbar,
             status = ORACLE_BREAKDOWN;
             break;
         }
-        /* D' = D + 2 (D^2 Dbar - c D Dbar) */
-        for (int64_t e = 0; e < MM; ++e) {
-            const double d2dbar = X2[e] - X3[e];
-            const double ddbar = D[e] - X2[e];
-            T[e] = D[e] + 2.0 * (d2dbar - c * ddbar);
+        if (method == 0) {
+            /* eq. (hpcp3): D' = D + 2 (D^2 Dbar - c D Dbar) */
+            for (int64_t e = 0; e < MM; ++e) {
+                const double d2dbar = X2[e] - X3[e];
+                const double ddbar = D[e] - X2[e];
+                T[e] = D[e] + 2.0 * (d2dbar - c * ddbar);
+            }
+        } else if (c <= 0.5) {
+            /* eq. (pm1a) */
+            for (int64_t e = 0; e < MM; ++e)
+                T[e] = ((1.0 - 2.0 * c) * D[e] + (1.0 + c) * X2[e] - X3[e]) / (1.0 - c);
+        } else {
+            /* eq. (pm1b) */
+            for (int64_t e = 0; e < MM; ++e)
+                T[e] = ((1.0 + c) * X2[e] - X3[e]) / c;
         }
         double step = 0.0;
         for (int64_t i = 0; i < M; ++i)
@@ -241,6 +356,55 @@ int oracle_purify_from(int64_t M, int64_t N, double *D, double tol_ddbar,
     *iters = n;
     free(X2); free(X3); free(T);
     return status;
+}
+
+int oracle_purify_from(int64_t M, int64_t N, double *D, double tol_ddbar,
+                       double tol_idem, int max_iter, double *hist, int *iters)
+{
+    return oracle_purify_from_m(M, N, D, 0, tol_ddbar, tol_idem, max_iter, hist, iters);
+}
+
+/* c_0 of a guess: (Tr D^2 - Tr D^3) / (Tr D - Tr D^2), NaN unless
+ * Tr(D Dbar) > 0 (the recursion would stop or break down at n = 0). */
+static double first_c(int64_t M, const double *D)
+{
+    double *X2 = (double *)malloc(sizeof(double) * M * M);
+    double *X3 = (double *)malloc(sizeof(double) * M * M);
+    if (!X2 || !X3) { free(X2); free(X3); return NAN; }
+    oracle_matmul(M, D, D, X2);
+    oracle_matmul(M, X2, D, X3);
+    const double t1 = trace(M, D), t2 = trace(M, X2), t3 = trace(M, X3);
+    free(X2); free(X3);
+    return (t1 - t2) > 0.0 ? (t2 - t3) / (t1 - t2) : NAN;
+}
+
+/* Full solve with a method (0 HPCP, 1 PMCP) and an initial guess (0 PMCP
+ * guess, 1 hole-particle mix with alpha, 2 alpha search with delta).  A
+ * hole-particle guess whose c_0 lies outside [0,1] is replaced by the PMCP
+ * guess.  scal[0..4]: mu, slope beta, emin, emax, alpha used. */
+int oracle_purify_ex(int64_t M, int64_t N, const double *H, double emin, double emax,
+                     int method, int init_mode, double alpha, double delta, double tol_ddbar,
+                     double tol_idem, int max_iter, double *D, double *hist, int *iters,
+                     double *scal)
+{
+    if (isnan(emin) || isnan(emax)) oracle_gershgorin(M, H, &emin, &emax);
+    double sc[3] = {0.0, 0.0, 1.0};
+    int st;
+    if (init_mode == 0) {
+        st = oracle_initial_guess(M, N, H, emin, emax, D, &sc[0], &sc[1]);
+    } else {
+        st = oracle_initial_guess_hp(M, N, H, emin, emax, init_mode, alpha, delta, D, sc);
+        if (st == ORACLE_OK && N > 0 && N < M) {
+            const double c0 = first_c(M, D);
+            if (!(c0 >= 0.0 && c0 <= 1.0)) {
+                st = oracle_initial_guess(M, N, H, emin, emax, D, &sc[0], &sc[1]);
+                sc[2] = 1.0;
+            }
+        }
+    }
+    if (scal) { scal[0] = sc[0]; scal[1] = sc[1]; scal[2] = emin; scal[3] = emax; scal[4] = sc[2]; }
+    if (st != ORACLE_OK) { *iters = 0; return st; }
+    return oracle_purify_from_m(M, N, D, method, tol_ddbar, tol_idem, max_iter, hist, iters);
 }
 
 /* Initial guess from (H, N, bounds) followed by the recursion.  NaN bounds

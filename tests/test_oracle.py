@@ -356,3 +356,120 @@ def test_verify_quantities_closed_forms(oracle_lib):
     assert q["trace"] == pytest.approx(20, abs=1e-12) and q["fro2"] == pytest.approx(20, abs=1e-12)
     assert q["idem"] < 1e-13 and q["comm"] < 1e-13
     assert q["energy"] == pytest.approx(np.sort(w.lam)[:20].sum(), abs=1e-12)
+
+
+# ------------------------------------- PM recursion and hole-particle guesses
+
+def test_pmcp_step_conserves_trace_and_reduces_to_mcweeny(oracle_lib):
+    """eqs. (pm1a)/(pm1b): Tr D' = Tr D in both branches of c; a spectrum
+    symmetric about 1/2 (c = 1/2) gives McWeeny's 3D^2 - 2D^3 in both
+    recursions; and PMCP converges to the ground-state projector."""
+    M = 10
+    for lam, low in ((np.linspace(0.02, 0.6, M), True), (np.linspace(0.4, 0.98, M), False)):
+        D, _ = rand_sym_spectrum(M, lam, 5)
+        N = int(round(np.trace(D)))
+        r = oracle.purify_from(D, N, tol_ddbar=0.0, max_iter=1, method="pmcp")
+        assert (r.col("c")[0] <= 0.5) == low
+        assert abs(np.trace(r.D) - np.trace(D)) < 1e-12
+    lam = np.linspace(0.1, 0.9, M)
+    D, _ = rand_sym_spectrum(M, lam, 6)
+    mcw = 3 * D @ D - 2 * D @ D @ D
+    for method in ("pmcp", "hpcp"):
+        r = oracle.purify_from(D, 5, tol_ddbar=0.0, max_iter=1, method=method)
+        assert r.col("c")[0] == pytest.approx(0.5, abs=1e-14)
+        assert np.abs(r.D - mcw).max() < 1e-12
+    w = workloads.spectral(64, 20, 0.2, 11)
+    r = oracle.purify_ex(w.H, w.N, w.emin, w.emax, method="pmcp", tol_ddbar=0.0, tol_idem=1e-10)
+    assert r.status == oracle.OK
+    assert np.abs(r.D - oracle.projector_from_spectrum(w.Q, w.lam, w.N)).max() < 1e-9
+
+
+def test_hp_guess_is_a_slope_change_with_closed_form_moments(oracle_lib):
+    """eq. (hpcpguess) built from the particle and hole matrices equals
+    theta I + beta_a (mu I - H) with beta_a = a beta_min + (1-a) beta_max; its
+    trace is N for every alpha and Tr(D0+^2) = N theta + beta_a^2 ||H - mu I||_F^2."""
+    w = workloads.spectral(40, 12, 0.3, 9)
+    M, N = w.M, w.N
+    theta, mu = N / M, np.trace(w.H) / M
+    bt, bb = theta / (w.emax - mu), (1 - theta) / (mu - w.emin)
+    bmin, bmax = min(bt, bb), max(bt, bb)
+    S = np.sum((w.H - mu * np.eye(M)) ** 2)
+    for a in (0.0, 0.3, 0.5, 1.0):
+        D0, mu_o, slope, a_used = oracle.initial_guess_hp(w.H, N, w.emin, w.emax, "hp", alpha=a)
+        ba = a * bmin + (1 - a) * bmax
+        assert a_used == a and slope == pytest.approx(ba, rel=1e-14)
+        assert np.abs(D0 - (theta * np.eye(M) + ba * (mu * np.eye(M) - w.H))).max() < 1e-14
+        assert np.trace(D0) == pytest.approx(N, abs=1e-12)
+        assert np.sum(D0 * D0) == pytest.approx(N * theta + ba ** 2 * S, rel=1e-12)
+
+
+@pytest.mark.parametrize("N", [2, 6, 34, 38])
+def test_alpha_search_hits_its_target(oracle_lib, N):
+    """eq. (hpcpguessalpha): Tr(D0+^2) = N - delta N (theta < 1 - delta) or
+    N - delta (M - N) (theta > delta) at the searched alpha."""
+    M, delta = 40, 2.0 / 3.0
+    w = workloads.spectral(M, N, 0.3, 10)
+    D0, _, _, a = oracle.initial_guess_hp(w.H, N, w.emin, w.emax, "search", delta=delta)
+    target = N - delta * N if N / M < 1 - delta else N - delta * (M - N)
+    assert 0.0 < a < 1.0
+    assert np.sum(D0 * D0) == pytest.approx(target, rel=1e-10)
+
+
+def test_matrix_and_eigenvalue_routes_agree_for_every_method_and_guess(oracle_lib):
+    for theta in (0.01, 0.05, 0.3, 0.5, 0.95):
+        w = workloads.paper_diagonal(100, int(round(theta * 100)), 1.0, 3000)
+        for method in ("hpcp", "pmcp"):
+            for init in ("pmcp", "hp", "search"):
+                r = oracle.purify_ex(w.H, w.N, method=method, init=init)
+                s = oracle.scalar_map(w.lam, w.N, w.lam.min(), w.lam.max(), method=method,
+                                      init=init)
+                assert r.status == s["status"] == oracle.OK
+                assert r.iters == s["iters"] and abs(r.alpha - s["alpha"]) < 1e-12
+                # c_n is a ratio of trace differences, each accurate to ~1e-14 M
+                ddbar = np.abs(r.col("t1") - r.col("t2"))[:-1]
+                assert np.all(np.abs(r.col("c")[:-1] - s["c"]) <= 1e-12 + 1e-14 * 100 / ddbar)
+
+
+def test_fig3_hole_particle_claims(oracle_lib):
+    """The Fig. 3 discussion (values and readings in the golden file)."""
+    g = json.load(open(os.path.join(GOLDEN, "fig3_hole_particle.json")))
+    M = g["M"]
+
+    def counts(theta, method, init, fallback=True):
+        ps = []
+        for s in range(g["hamiltonians_per_point"]):
+            w = workloads.paper_diagonal(M, int(round(theta * M)), g["gap"], g["seed0"] + s)
+            if fallback:
+                r = oracle.scalar_map(w.lam, w.N, w.lam.min(), w.lam.max(), tol_ddbar=g["tol_ddbar"],
+                                      method=method, init=init)
+                ps.append(r["iters"] if r["status"] == oracle.OK else None)
+            else:   # the raw alpha = 1/2 guess, no fall-back
+                D0, _, _, _ = oracle.initial_guess_hp(w.H, w.N, w.lam.min(), w.lam.max(), "hp")
+                r = oracle.purify_from(D0, w.N, tol_ddbar=g["tol_ddbar"])
+                ps.append(r.iters if r.status == oracle.OK else None)
+        return ps
+
+    def mean(ps):
+        assert all(p is not None for p in ps)
+        return float(np.mean(ps))
+
+    r05 = mean(counts(0.05, "pmcp", "pmcp")) / mean(counts(0.05, "hpcp", "pmcp"))
+    lo, hi = g["theta_0.05"]["ratio_range"]
+    assert lo <= r05 <= hi, r05
+    h01 = mean(counts(0.01, "hpcp", "search"))
+    p01 = mean(counts(0.01, "pmcp", "search"))
+    t = g["theta_0.01_search"]
+    assert abs(h01 - t["hpcp"]) <= t["hpcp_abs_tol"], h01
+    assert t["ratio_range"][0] <= p01 / h01 <= t["ratio_range"][1], p01 / h01
+    flat = [mean(counts(th, "hpcp", "hp")) for th in g["alpha_half_flat_thetas"]]
+    assert max(flat) - min(flat) <= g["alpha_half_flat_spread_max"], flat
+    for th in g["alpha_half_runaway_thetas"]:
+        raw = counts(th, "hpcp", "hp", fallback=False)
+        assert sum(p is None for p in raw) > len(raw) // 2
+    for th in g["search_pole_thetas"]:
+        extra = mean(counts(th, "hpcp", "search")) - mean(counts(th, "hpcp", "hp"))
+        assert g["search_pole_extra_range"][0] <= extra <= g["search_pole_extra_range"][1], extra
+    # the search fixes the extreme fillings for both recursions
+    for th in (0.01, 0.05, 0.95):
+        for m in ("hpcp", "pmcp"):
+            assert mean(counts(th, m, "search")) < mean(counts(th, m, "pmcp"))
