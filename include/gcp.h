@@ -101,7 +101,27 @@ typedef struct {
                                below the early encoding's rounding floor. */
     int32_t pad;
     double switch_ddbar;   /* see late_precision (default 0) */
+    int32_t method;        /* GCP_METHOD_HPCP (default): eq. (hpcp3); GCP_METHOD_PMCP: the
+                              Palser-Manolopoulos canonical purification of the
+                              appendix, eqs. (pm1a) (c <= 1/2) and (pm1b) (c > 1/2) */
+    int32_t init_mode;     /* GCP_INIT_PMCP (default): eq. (pmcpguess), beta = min;
+                              GCP_INIT_HP: the hole-particle guess of eq. (hpcpguess),
+                              alpha D0 + (1 - alpha)(I - Dbar0) = theta I
+                              + (alpha beta_min + (1 - alpha) beta_max)(mu I - H);
+                              GCP_INIT_HP_SEARCH: alpha chosen so that Tr(D0^2) = N - delta N
+                              (theta < 1 - delta) or N - delta (M - N) (theta > delta), else
+                              alpha = 1/2 (eq. (hpcpguessalpha); closed form through
+                              ||H - mu I||_F^2).  Both hole-particle guesses cost one extra
+                              product in gcp_init, which checks c_0 and falls back to
+                              alpha = 1 (the PMCP guess) when Tr(D0 Dbar0) <= 0 or c_0 is
+                              outside [0, 1] (the runaway the paper reports for alpha = 1/2
+                              at extreme fillings). */
+    double alpha;          /* GCP_INIT_HP mixing coefficient, in [0, 1] (default 0.5) */
+    double delta;          /* GCP_INIT_HP_SEARCH constant, in (1/2, 1) (default 2/3) */
 } gcp_options;
+
+enum { GCP_METHOD_HPCP = 0, GCP_METHOD_PMCP = 1 };
+enum { GCP_INIT_PMCP = 0, GCP_INIT_HP = 1, GCP_INIT_HP_SEARCH = 2 };
 
 typedef struct {
     int32_t status;      /* gcp_status of the solve */
@@ -155,7 +175,9 @@ int gcp_purify(gcp_ctx *ctx, void *D, int32_t dtype, int64_t ldd, gcp_result *ou
  * M x M, leading dimension ldg, dtype gcp_dtype; read as its symmetric part),
  * writes dL/dH (device, M x M, leading dimension ldh, same dtype), the
  * gradient with respect to symmetric perturbations of H, for the p updates
- * that gcp_purify applied, whatever its status.
+ * that gcp_purify applied, whatever its status.  Supported for the HPCP
+ * recursion with the PMCP or the fixed-alpha hole-particle guess; the PMCP
+ * recursion and the alpha search return UNSUPPORTED.
  *   - Each update of eq. (hpcp3), D' = (1-2c) D + (2+2c) D^2 - 2 D^3 with
  *     c = (T2 - T3)/(T1 - T2), is differentiated including the dependence of
  *     c on D; this costs two symmetric and two general M x M products per
@@ -201,9 +223,11 @@ int gcp_verify(gcp_ctx *ctx, const void *D, int32_t dtype, int64_t ldd, const do
 #define GCP_HIST_COLS 9
 int gcp_get_history(const gcp_ctx *ctx, double *rows, int32_t max_rows, int32_t *n_rows);
 
-/* Scalars of the last gcp_init: mu, beta, emin, emax (bounds actually used). */
+/* Scalars of the last gcp_init: mu, the slope beta of D_0 = theta I + beta (mu I - H),
+ * emin, emax (bounds actually used) and alpha (1 for the PMCP guess or after the
+ * fall-back).  Any output pointer may be NULL. */
 int gcp_get_init_scalars(const gcp_ctx *ctx, double *mu, double *beta, double *emin,
-                         double *emax);
+                         double *emax, double *alpha);
 
 /* Text of the last error on this context (or of the last failed gcp_create
  * when ctx is NULL).  The pointer stays valid until the next call. */

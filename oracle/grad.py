@@ -13,12 +13,15 @@ c = (T2 - T3)/(T1 - T2), T_k = Tr D^k.  For symmetric D and Gbar':
     grad_c = [(2 D - 3 D^2) - c (I - 2 D)] / (T1 - T2)
 
 The initial guess of eqs. (dmguess),(pmcpguess) has D0 = theta I + beta(mu)
-(mu I - H), with mu = Tr(H)/M and the bounds held fixed:
+(mu I - H), with mu = Tr(H)/M and the bounds held fixed (the hole-particle
+guess of eq. (hpcpguess) with a fixed alpha has the same form with
+beta = alpha beta_min + (1 - alpha) beta_max):
 
     dL/dH = -beta Gbar0 + (I/M) [beta Tr Gbar0 + beta'(mu) <Gbar0, mu I - H>],
 
 where beta' is that of the active branch of the min:
-theta/(emax - mu)^2 or -(1-theta)/(mu - emin)^2.
+theta/(emax - mu)^2 or -(1-theta)/(mu - emin)^2 (for the hole-particle guess,
+alpha times the min branch's plus 1 - alpha times the max branch's).
 
 ``adjoint`` is written in FP64 numpy with library matmuls.  It is pinned by
 central finite differences of the oracle's forward recursion, at a fixed
@@ -29,12 +32,17 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import initial_guess
+from . import initial_guess, initial_guess_hp
 
 
-def forward_iterates(H: np.ndarray, N: int, emin: float, emax: float, p: int):
-    """D_0..D_p of eq. (hpcp3) (plain FP64, symmetrised each step) and c_0..c_{p-1}."""
-    D, mu, beta = initial_guess(H, N, emin, emax)
+def forward_iterates(H: np.ndarray, N: int, emin: float, emax: float, p: int,
+                     alpha: float = 1.0):
+    """D_0..D_p of eq. (hpcp3) (plain FP64, symmetrised each step) and c_0..c_{p-1};
+    alpha < 1 starts from the hole-particle guess of eq. (hpcpguess)."""
+    if alpha == 1.0:
+        D, mu, beta = initial_guess(H, N, emin, emax)
+    else:
+        D, mu, beta, _ = initial_guess_hp(H, N, emin, emax, "hp", alpha=alpha)
     Ds, cs, t12 = [D], [], []
     for _ in range(p):
         X2 = D @ D
@@ -49,10 +57,13 @@ def forward_iterates(H: np.ndarray, N: int, emin: float, emax: float, p: int):
     return Ds, np.array(cs), np.array(t12), mu, beta
 
 
-def adjoint(H: np.ndarray, N: int, emin: float, emax: float, p: int, Gbar_p: np.ndarray):
-    """dL/dH for L(D_p), given Gbar_p = dL/dD_p (symmetrised here)."""
+def adjoint(H: np.ndarray, N: int, emin: float, emax: float, p: int, Gbar_p: np.ndarray,
+            alpha: float = 1.0):
+    """dL/dH for L(D_p), given Gbar_p = dL/dD_p (symmetrised here).  alpha < 1:
+    the hole-particle guess, slope alpha beta_min + (1 - alpha) beta_max with
+    alpha fixed."""
     M = H.shape[0]
-    Ds, cs, t12, mu, beta = forward_iterates(H, N, emin, emax, p)
+    Ds, cs, t12, mu, beta = forward_iterates(H, N, emin, emax, p, alpha)
     G = 0.5 * (Gbar_p + Gbar_p.T)
     I = np.eye(M)
     for n in range(p - 1, -1, -1):
@@ -69,17 +80,19 @@ def adjoint(H: np.ndarray, N: int, emin: float, emax: float, p: int, Gbar_p: np.
     theta = N / M
     if 0 < N < M:
         bt, bb = theta / (emax - mu), (1 - theta) / (mu - emin)
-        dbeta = theta / (emax - mu) ** 2 if bt <= bb else -(1 - theta) / (mu - emin) ** 2
+        dbt, dbb = theta / (emax - mu) ** 2, -(1 - theta) / (mu - emin) ** 2
+        dmin, dmax = (dbt, dbb) if bt <= bb else (dbb, dbt)
+        dbeta = alpha * dmin + (1 - alpha) * dmax
     else:
         dbeta = 0.0
     dH = -beta * G + I / M * (beta * np.trace(G) + dbeta * np.sum(G * (mu * I - H)))
     return 0.5 * (dH + dH.T)
 
 
-def loss_fd(H, N, emin, emax, p, P, dH, h=1e-6):
+def loss_fd(H, N, emin, emax, p, P, dH, h=1e-6, alpha=1.0):
     """Central difference of L = Tr(D_p P) along the symmetric direction dH."""
     def L(Hx):
-        Ds, *_ = forward_iterates(Hx, N, emin, emax, p)
+        Ds, *_ = forward_iterates(Hx, N, emin, emax, p, alpha)
         return float(np.sum(Ds[-1] * P))
     return (L(H + h * dH) - L(H - h * dH)) / (2 * h)
 

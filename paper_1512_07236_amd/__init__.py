@@ -69,7 +69,13 @@ class Options(ctypes.Structure):
                 ("fold_every", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("keep_iterates", ctypes.c_int32), ("bwd_precision", ctypes.c_int32),
                 ("late_precision", ctypes.c_int32), ("pad", ctypes.c_int32),
-                ("switch_ddbar", ctypes.c_double)]
+                ("switch_ddbar", ctypes.c_double), ("method", ctypes.c_int32),
+                ("init_mode", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("delta", ctypes.c_double)]
+
+
+METHODS = {"hpcp": 0, "pmcp": 1}           # the recursion
+INITS = {"pmcp": 0, "hp": 1, "search": 2}  # the initial guess
 
 
 class CResult(ctypes.Structure):
@@ -121,7 +127,7 @@ def load_library() -> ctypes.CDLL:
     L.gcp_verify.restype = ctypes.c_int
     L.gcp_get_history.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(i32)]
     L.gcp_get_history.restype = ctypes.c_int
-    L.gcp_get_init_scalars.argtypes = [vp] + [ctypes.POINTER(ctypes.c_double)] * 4
+    L.gcp_get_init_scalars.argtypes = [vp] + [ctypes.POINTER(ctypes.c_double)] * 5
     L.gcp_get_init_scalars.restype = ctypes.c_int
     L.gcp_last_error.argtypes = [vp]
     L.gcp_last_error.restype = ctypes.c_char_p
@@ -171,7 +177,8 @@ class Context:
     def __init__(self, M: int, precision="fp64", max_iter: int = 100, tol_ddbar: float = 1e-6,
                  tol_idem: float = 0.0, fold_every: int = 0, profile: bool = False,
                  keep_iterates: bool = False, bwd_precision="fp64", late_precision=None,
-                 switch_ddbar: float = 0.0, stream=None):
+                 switch_ddbar: float = 0.0, method: str = "hpcp", init: str = "pmcp",
+                 alpha: float = 0.5, delta: float = 2.0 / 3.0, stream=None):
         L = load_library()
         self._L = L
         self.M = int(M)
@@ -187,6 +194,10 @@ class Context:
         o.bwd_precision = int(Precision.parse(bwd_precision))
         o.late_precision = -1 if late_precision is None else int(Precision.parse(late_precision))
         o.switch_ddbar = float(switch_ddbar)
+        o.method = METHODS[method]
+        o.init_mode = INITS[init]
+        o.alpha = float(alpha)
+        o.delta = float(delta)
         self.options = o
         self._stream = stream
         h = ctypes.c_void_p()
@@ -276,9 +287,9 @@ class Context:
         return rows
 
     def init_scalars(self) -> dict:
-        v = [ctypes.c_double() for _ in range(4)]
+        v = [ctypes.c_double() for _ in range(5)]
         self._check(self._L.gcp_get_init_scalars(self._h, *[ctypes.byref(x) for x in v]))
-        return dict(zip(("mu", "beta", "emin", "emax"), (x.value for x in v)))
+        return dict(zip(("mu", "beta", "emin", "emax", "alpha"), (x.value for x in v)))
 
     def close(self) -> None:
         if getattr(self, "_h", None):

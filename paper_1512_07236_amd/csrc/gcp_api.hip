@@ -86,7 +86,9 @@ struct gcp_ctx {
   // init state
   bool inited = false;
   int64_t N = 0;
-  double mu = NAN, beta = NAN, emin = NAN, emax = NAN;
+  double mu = NAN, beta = NAN, emin = NAN, emax = NAN, alpha = 1.0;
+  double beta_min = 0.0, beta_max = 0.0;
+  bool alpha_searched = false;   // alpha from the search's target (depends on H)
   double t1_0 = NAN, t2_0 = NAN;
   void *D0p = nullptr;      // copy of the D_0 planes so purify can be re-run
   double *dg0 = nullptr, *rD0 = nullptr, *d20 = nullptr;
@@ -197,6 +199,10 @@ extern "C" int gcp_options_default(gcp_options *opt) {
   opt->bwd_precision = GCP_FP64;
   opt->late_precision = -1;
   opt->switch_ddbar = 0.0;
+  opt->method = GCP_METHOD_HPCP;
+  opt->init_mode = GCP_INIT_PMCP;
+  opt->alpha = 0.5;
+  opt->delta = 2.0 / 3.0;
   return GCP_OK;
 }
 
@@ -228,6 +234,12 @@ extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void
   }
   if (o.late_precision < -1 || o.late_precision > GCP_BF16X6 || !(o.switch_ddbar >= 0.0)) {
     g_create_error = "gcp_create: late_precision must be -1 or a precision, switch_ddbar >= 0";
+    return GCP_ERR_INVALID_ARG;
+  }
+  if (o.method < GCP_METHOD_HPCP || o.method > GCP_METHOD_PMCP || o.init_mode < GCP_INIT_PMCP ||
+      o.init_mode > GCP_INIT_HP_SEARCH || !(o.alpha >= 0.0 && o.alpha <= 1.0) ||
+      !(o.delta > 0.5 && o.delta < 1.0)) {
+    g_create_error = "gcp_create: method, init_mode, alpha in [0,1] or delta in (1/2,1) invalid";
     return GCP_ERR_INVALID_ARG;
   }
   gcp_ctx *c = new (std::nothrow) gcp_ctx();
@@ -374,6 +386,29 @@ static int reduce(gcp_ctx *c, const double *part, int nslots, int mode, double *
   return GCP_OK;
 }
 
+static int build_guess(gcp_ctx *c, const double *H, int64_t ldh, double theta, double beta,
+                       double mu);
+static int first_traces(gcp_ctx *c);
+
+// Fields of the product launch that do not change within a solve.
+static void setup_gemm(gcp_ctx *c, GemmArgs &g, int pi) {
+  const gcp_ctx::PrecCfg &q = c->pc[pi];
+  g.Mp = c->Mp;
+  g.pstride = c->Mp * c->Mp;
+  g.nt = c->nt;
+  g.fold = q.fold;
+  g.nfull = q.nfull;
+  g.nsplit = q.nsplit;
+  g.method = c->opt.method;
+  g.ws = c->g16_ws;
+  g.cnt = c->g16_cnt;
+  g.part = c->part;
+  g.tpart = c->tpart;
+  g.s2 = c->s2;
+  g.d3 = c->d3;
+  g.coef = &c->sc->c;
+}
+
 extern "C" int gcp_init(gcp_ctx *c, const double *H, int64_t ldh, int64_t N, double emin,
                         double emax) {
   if (!c) return GCP_ERR_INVALID_ARG;
@@ -402,21 +437,80 @@ extern "C" int gcp_init(gcp_ctx *c, const double *H, int64_t ldh, int64_t N, dou
   const double M = (double)c->M;
   const double theta = (double)N / M;
   const double mu = trH / M;
-  double beta = 0.0;
+  double beta = 0.0, bmin = 0.0, bmax = 0.0, alpha = 1.0;
+  bool searched = false;
   if (N > 0 && N < c->M) {
     if (!(emin < mu && mu < emax)) {
       c->err = "gcp_init: mu = Tr(H)/M must lie strictly inside (emin, emax)";
       return GCP_ERR_INVALID_ARG;
     }
     const double bt = theta / (emax - mu), bb = (1.0 - theta) / (mu - emin);
-    beta = bt < bb ? bt : bb;
+    bmin = bt < bb ? bt : bb;
+    bmax = bt < bb ? bb : bt;
+    beta = bmin;
+    if (c->opt.init_mode == GCP_INIT_HP) {
+      alpha = c->opt.alpha;
+    } else if (c->opt.init_mode == GCP_INIT_HP_SEARCH) {
+      // Tr(D0^2) = N theta + beta^2 ||H - mu I||_F^2 for D0 = theta I + beta (mu I - H):
+      // the target fixes beta, and beta = alpha beta_min + (1 - alpha) beta_max fixes alpha
+      const double delta = c->opt.delta;
+      double target = NAN;
+      if (theta < 1.0 - delta) target = (double)N - delta * (double)N;
+      else if (theta > delta) target = (double)N - delta * (double)(c->M - N);
+      if (std::isnan(target)) {
+        alpha = 0.5;
+      } else {
+        HIPCHK(c, launch_hdev(H, ldh, c->M, c->Mp, mu, c->part, &c->sc->hstat[3], c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const double S = c->sc_host->hstat[3];
+        const double b2 = (target - (double)N * theta) / S;
+        if (!(b2 > 0.0) || !(S > 0.0)) {
+          alpha = 1.0;
+        } else if (bmax > bmin) {
+          alpha = (bmax - std::sqrt(b2)) / (bmax - bmin);
+          searched = alpha > 0.0 && alpha < 1.0;
+          alpha = alpha < 0.0 ? 0.0 : (alpha > 1.0 ? 1.0 : alpha);
+        }
+      }
+    }
+    beta = alpha * bmin + (1.0 - alpha) * bmax;
   }
   c->N = N;
   c->mu = mu;
-  c->beta = beta;
   c->emin = emin;
   c->emax = emax;
+  c->beta_min = bmin;
+  c->beta_max = bmax;
 
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    int st = build_guess(c, H, ldh, theta, beta, mu);
+    if (st != GCP_OK) return st;
+    if (c->opt.init_mode == GCP_INIT_PMCP || !(N > 0 && N < c->M) || attempt == 1) break;
+    // hole-particle guess: one product gives c_0; Tr(D0 Dbar0) <= 0 or c_0
+    // outside [0, 1] means the recursion would run away: use alpha = 1
+    st = first_traces(c);
+    if (st != GCP_OK) return st;
+    const double t1 = c->sc_host->t1, t2 = c->sc_host->t2, t3 = c->sc_host->t3;
+    const double c0 = (t2 - t3) / (t1 - t2);
+    if (t1 - t2 > 0.0 && c0 >= 0.0 && c0 <= 1.0) break;
+    alpha = 1.0;
+    beta = bmin;
+    searched = false;
+  }
+  c->alpha = alpha;
+  c->alpha_searched = searched;
+  c->beta = beta;
+  (void)vec;
+  c->inited = true;
+  return GCP_OK;
+}
+
+// D_0 = theta I + beta (mu I - H) in the main encoding, its FP64 diagonal and
+// the traces T1, T2 (kept in t1_0, t2_0).
+static int build_guess(gcp_ctx *c, const double *H, int64_t ldh, double theta, double beta,
+                       double mu) {
   InitArgs a{};
   a.H = H;
   a.ldh = ldh;
@@ -437,19 +531,38 @@ extern "C" int gcp_init(gcp_ctx *c, const double *H, int64_t ldh, int64_t N, dou
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->t1_0 = c->sc_host->t1;
   c->t2_0 = c->sc_host->t2;
-  (void)vec;
-  c->inited = true;
+  return GCP_OK;
+}
+
+// T1, T2, T3 of D_0 (one D^2 product, as the first step of gcp_purify) into
+// c->sc_host.
+static int first_traces(gcp_ctx *c) {
+  GemmArgs g{};
+  setup_gemm(c, g, 0);
+  g.mode = 0;
+  g.A = c->D0p;
+  g.B = c->D0p;
+  g.out = c->X2p;
+  g.dg = c->dg0;
+  g.rD = c->rD0;
+  g.d2 = c->d20;
+  HIPCHK(c, launch_gemm(c->pc[0].prec, g, c->stream));
+  int st = reduce(c, c->part, c->nt, 1, c->d3, nullptr, c->tpart, c->pc[0].ntpart, 0);
+  if (st != GCP_OK) return st;
+  HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return GCP_OK;
 }
 
 extern "C" int gcp_get_init_scalars(const gcp_ctx *c, double *mu, double *beta, double *emin,
-                                    double *emax) {
+                                    double *emax, double *alpha) {
   if (!c) return GCP_ERR_INVALID_ARG;
   if (!c->inited) return GCP_ERR_STATE;
   if (mu) *mu = c->mu;
   if (beta) *beta = c->beta;
   if (emin) *emin = c->emin;
   if (emax) *emax = c->emax;
+  if (alpha) *alpha = c->alpha;
   return GCP_OK;
 }
 
@@ -530,16 +643,7 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
     return GCP_OK;
   };
 
-  g.Mp = c->Mp;
-  g.pstride = PS;
-  g.nt = c->nt;
-  g.ws = c->g16_ws;
-  g.cnt = c->g16_cnt;
-  g.part = c->part;
-  g.tpart = c->tpart;
-  g.s2 = c->s2;
-  g.d3 = c->d3;
-  g.coef = &c->sc->c;
+  setup_gemm(c, g, 0);
 
   int status = 0, n = 0;
   for (;; ++n) {
@@ -649,6 +753,10 @@ extern "C" int gcp_backward(gcp_ctx *c, const void *dLdD, int64_t ldg, void *dLd
     c->err = "gcp_backward: needs a gcp_purify with keep_iterates = 1 after the last gcp_init";
     return GCP_ERR_STATE;
   }
+  if (c->opt.method != GCP_METHOD_HPCP || c->alpha_searched) {
+    c->err = "gcp_backward: the adjoint covers the HPCP recursion with a fixed-alpha guess";
+    return GCP_ERR_UNSUPPORTED;
+  }
   if (!dLdD || !dLdH || ldg < c->M || ldh < c->M ||
       (dtype != GCP_DTYPE_F64 && dtype != GCP_DTYPE_F32)) {
     c->err = "gcp_backward: need non-NULL buffers, ldg >= M, ldh >= M and dtype F64 or F32";
@@ -734,9 +842,13 @@ extern "C" int gcp_backward(gcp_ctx *c, const void *dLdD, int64_t ldg, void *dLd
   ia.beta = c->beta;
   ia.dbeta = 0.0;
   if (c->N > 0 && c->N < c->M) {
+    // beta = alpha beta_min + (1 - alpha) beta_max with alpha fixed; each
+    // branch differentiated through mu with the bounds held fixed
     const double bt = ia.theta / (c->emax - c->mu), bb = (1.0 - ia.theta) / (c->mu - c->emin);
-    ia.dbeta = bt <= bb ? ia.theta / ((c->emax - c->mu) * (c->emax - c->mu))
-                        : -(1.0 - ia.theta) / ((c->mu - c->emin) * (c->mu - c->emin));
+    const double dbt = ia.theta / ((c->emax - c->mu) * (c->emax - c->mu));
+    const double dbb = -(1.0 - ia.theta) / ((c->mu - c->emin) * (c->mu - c->emin));
+    const double dmin = bt <= bb ? dbt : dbb, dmax = bt <= bb ? dbb : dbt;
+    ia.dbeta = c->alpha * dmin + (1.0 - c->alpha) * dmax;
   }
   ia.rows = c->bvec;
   ia.sums = c->bvec + 2 * c->Mp + 1;

@@ -30,7 +30,7 @@ struct GemmArgs {
   // last of them to finish (per-pair arrival counters in cnt, self-resetting)
   int nfull;
   int nsplit;
-  int pad;
+  int method;          // 0 HPCP, 1 PMCP (update coefficients of mode 1)
   float *ws;
   unsigned *cnt;
   const double *dg;    // diag(D) FP64
@@ -143,5 +143,9 @@ hipError_t launch_convert(int pa, int pb, const void *in, const double *diag, vo
 hipError_t launch_reduce(const RedArgs &a, hipStream_t st);
 hipError_t launch_hstats(const double *H, int64_t ldh, int64_t M, double *lo, double *hi,
                          double *hd, double *out, hipStream_t st);
+// out[0] = || (H + H^T)/2 - mu I ||_F^2 over M x M (fixed order); scratch holds
+// (Mp/64)^2 block partials.
+hipError_t launch_hdev(const double *H, int64_t ldh, int64_t M, int64_t Mp, double mu,
+                       double *scratch, double *out, hipStream_t st);
 
 }  // namespace gcp

@@ -23,6 +23,30 @@
 
 namespace gcp {
 
+// D' = a D + b D^2 + e D^3 for the recursion `method` at coefficient c:
+// HPCP, eq. (hpcp3) with Dbar = I - D: a = 1 - 2c, b = 2 + 2c, e = -2;
+// PMCP, eq. (pm1a) for c <= 1/2: (1 - 2c, 1 + c, -1) / (1 - c),
+//       eq. (pm1b) for c > 1/2:  (0, 1 + c, -1) / c.
+// Every choice keeps a Tr D + b Tr D^2 + e Tr D^3 = Tr D for this c.
+__device__ __forceinline__ void update_coefs(int method, double c, double &a, double &b,
+                                             double &e) {
+  if (method == 0) {
+    a = 1.0 - 2.0 * c;
+    b = 2.0 + 2.0 * c;
+    e = -2.0;
+  } else if (c <= 0.5) {
+    const double r = 1.0 / (1.0 - c);
+    a = (1.0 - 2.0 * c) * r;
+    b = (1.0 + c) * r;
+    e = -r;
+  } else {
+    const double r = 1.0 / c;
+    a = 0.0;
+    b = (1.0 + c) * r;
+    e = -r;
+  }
+}
+
 // FP64 / FP32 product kernel: one 128 x 128 upper-triangle tile per block of
 // 4 waves (2 x 2 grid of 64 x 64), MFMA 16x16x4, two blocks per CU.
 template <int P>
@@ -57,12 +81,8 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) rowacc[bi][r] = 0.0;
   }
-  double a_coef = 0.0, b_coef = 0.0;
-  if (g.mode == 1) {
-    const double c = g.coef[0];
-    a_coef = 1.0 - 2.0 * c;
-    b_coef = 2.0 + 2.0 * c;
-  }
+  double a_coef = 0.0, b_coef = 0.0, e_coef = 0.0;
+  if (g.mode == 1) update_coefs(g.method, g.coef[0], a_coef, b_coef, e_coef);
 
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
@@ -97,7 +117,7 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
           double Dm, dn;
           if (i == j) {
             Dm = g.dg[i];
-            dn = a_coef * Dm + b_coef * g.d2[i] - 2.0 * g.d3[i];
+            dn = a_coef * Dm + b_coef * g.d2[i] + e_coef * g.d3[i];
           } else {
             T xp[NP];
 #pragma unroll
@@ -106,7 +126,7 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
             const double X2m = E::dec(xp);
             // X3 = (X2_enc + diag(s2)) (D_enc + diag(rD))
             const double x3 = v + X2m * g.rD[j] + g.s2[i] * Dm;
-            dn = a_coef * Dm + b_coef * X2m - 2.0 * x3;
+            dn = a_coef * Dm + b_coef * X2m + e_coef * x3;
           }
           E::enc(dn, op);
           const double dnm = (i == j) ? dn : E::dec(op);
@@ -470,12 +490,8 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
   const int64_t i0 = arow0 + br * 8;
   const double S = E::PROD_SCALE;
   T *__restrict__ Og = (T *)g.out;
-  double a_coef = 0.0, b_coef = 0.0;
-  if (g.mode == 1) {
-    const double c = g.coef[0];
-    a_coef = 1.0 - 2.0 * c;
-    b_coef = 2.0 + 2.0 * c;
-  }
+  double a_coef = 0.0, b_coef = 0.0, e_coef = 0.0;
+  if (g.mode == 1) update_coefs(g.method, g.coef[0], a_coef, b_coef, e_coef);
   double rsum[8], csum[8], tsum = 0.0;
 #pragma unroll
   for (int r = 0; r < 8; ++r) rsum[r] = csum[r] = 0.0;
@@ -520,7 +536,7 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
           double Dm, dn;
           if (i == j) {
             Dm = g.dg[i];
-            dn = a_coef * Dm + b_coef * g.d2[i] - 2.0 * g.d3[i];
+            dn = a_coef * Dm + b_coef * g.d2[i] + e_coef * g.d3[i];
           } else {
             T xp[NP];
 #pragma unroll
@@ -528,7 +544,7 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
             Dm = E::dec(dp);
             const double X2m = E::dec(xp);
             const double x3 = v + X2m * g.rD[j] + g.s2[i] * Dm;
-            dn = a_coef * Dm + b_coef * X2m - 2.0 * x3;
+            dn = a_coef * Dm + b_coef * X2m + e_coef * x3;
           }
           E::enc(dn, op);
           const double dnm = (i == j) ? dn : E::dec(op);
@@ -705,6 +721,50 @@ __global__ __launch_bounds__(256) void k_hfinal(const double *lo, const double *
     out[1] = smax[0];
     out[2] = ssum[0];
   }
+}
+
+// ||(H + H^T)/2 - mu I||_F^2 (the alpha search of the hole-particle guess):
+// 64 x 64 tiles, one partial per tile, then a fixed-order sum.
+__global__ __launch_bounds__(256) void k_hdev(const double *__restrict__ H, int64_t ldh, int64_t M,
+                                              double mu, double *part) {
+  __shared__ double hs[64][65], ht[64][65], red[256];
+  const int64_t I = (int64_t)blockIdx.y * 64, J = (int64_t)blockIdx.x * 64;
+  const int tid = threadIdx.x, row = tid >> 2, c0 = (tid & 3) * 16;
+  for (int c = 0; c < 16; ++c) {
+    const int64_t gi = I + row, gj = J + c0 + c;
+    hs[row][c0 + c] = (gi < M && gj < M) ? H[gi * ldh + gj] : 0.0;
+    const int64_t ti = J + row, tj = I + c0 + c;
+    ht[row][c0 + c] = (ti < M && tj < M) ? H[ti * ldh + tj] : 0.0;
+  }
+  __syncthreads();
+  double s = 0.0;
+  for (int c = 0; c < 16; ++c) {
+    const int64_t i = I + row, j = J + c0 + c;
+    if (i < M && j < M) {
+      const double x = 0.5 * (hs[row][c0 + c] + ht[c0 + c][row]) - (i == j ? mu : 0.0);
+      s += x * x;
+    }
+  }
+  red[tid] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_hdev_sum(const double *part, int n, double *out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int t = threadIdx.x; t < n; t += 256) s += part[t];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
 }
 
 // ------------------------------------------------------------ initial guess
@@ -1002,6 +1062,14 @@ hipError_t launch_hstats(const double *H, int64_t ldh, int64_t M, double *lo, do
                          double *hd, double *out, hipStream_t st) {
   k_hstats<<<(unsigned)M, 256, 0, st>>>(H, ldh, M, lo, hi, hd);
   k_hfinal<<<1, 256, 0, st>>>(lo, hi, hd, M, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_hdev(const double *H, int64_t ldh, int64_t M, int64_t Mp, double mu,
+                       double *scratch, double *out, hipStream_t st) {
+  const unsigned nb = (unsigned)(Mp / 64);
+  k_hdev<<<dim3(nb, nb), 256, 0, st>>>(H, ldh, M, mu, scratch);
+  k_hdev_sum<<<1, 256, 0, st>>>(scratch, (int)(nb * nb), out);
   return hipGetLastError();
 }
 

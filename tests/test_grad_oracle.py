@@ -126,3 +126,17 @@ def test_daleckii_krein_matches_finite_differences_of_projector(oracle_lib):
 
     fd = (L(H + h * dH) - L(H - h * dH)) / (2 * h)
     assert abs(fd - np.sum(dk * dH)) <= 1e-7 * max(1.0, abs(fd))
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.5, 0.8])
+def test_adjoint_hole_particle_guess_matches_finite_differences(oracle_lib, alpha):
+    """The fixed-alpha hole-particle guess: the slope alpha beta_min +
+    (1 - alpha) beta_max moves with mu through both branches."""
+    M, N, p = 16, 7, 3
+    H, lo, hi = _case(M, N, 41)
+    P = W.sym_gaussian(M, 42)
+    g = grad.adjoint(H, N, lo, hi, p, P, alpha=alpha)
+    for dH in (W.sym_gaussian(M, 43), np.eye(M)):
+        fd = grad.loss_fd(H, N, lo, hi, p, P, dH, h=1e-5, alpha=alpha)
+        an = float(np.sum(g * dH))
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (alpha, fd, an)
