@@ -118,6 +118,13 @@ typedef struct {
                               at extreme fillings). */
     double alpha;          /* GCP_INIT_HP mixing coefficient, in [0, 1] (default 0.5) */
     double delta;          /* GCP_INIT_HP_SEARCH constant, in (1/2, 1) (default 2/3) */
+    int32_t hole;          /* 1: purify the hole matrix Dbar = I - D instead (the alternative
+                              the paper gives before eq. (hpcpguess)): Dbar_0 = I - D_0 of
+                              the selected guess, trace M - N, and D = I - Dbar_p is returned.
+                              HPCP is hole-particle symmetric (the same iterates up to
+                              rounding); PMCP is not.  History rows and gcp_backward's
+                              kept iterates are those of Dbar; result t1/t2 are of D. */
+    int32_t pad2;
 } gcp_options;
 
 enum { GCP_METHOD_HPCP = 0, GCP_METHOD_PMCP = 1 };

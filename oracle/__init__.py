@@ -74,8 +74,8 @@ def lib():
         L.oracle_purify.argtypes = [i64, i64, P, dbl, dbl, dbl, dbl, cint, P, P,
                                     ctypes.POINTER(cint), P]
         L.oracle_purify.restype = cint
-        L.oracle_purify_ex.argtypes = [i64, i64, P, dbl, dbl, cint, cint, dbl, dbl, dbl, dbl,
-                                       cint, P, P, ctypes.POINTER(cint), P]
+        L.oracle_purify_ex.argtypes = [i64, i64, P, dbl, dbl, cint, cint, dbl, dbl, cint, dbl,
+                                       dbl, cint, P, P, ctypes.POINTER(cint), P]
         L.oracle_purify_ex.restype = cint
         L.oracle_initial_guess_hp.argtypes = [i64, i64, P, dbl, dbl, cint, dbl, dbl, P, P]
         L.oracle_initial_guess_hp.restype = cint
@@ -166,10 +166,11 @@ def purify(H: np.ndarray, N: int, emin: float = float("nan"), emax: float = floa
 def purify_ex(H: np.ndarray, N: int, emin: float = float("nan"), emax: float = float("nan"),
               method: str = "hpcp", init: str = "pmcp", alpha: float = 0.5,
               delta: float = 2.0 / 3.0, tol_ddbar: float = 1e-6, tol_idem: float = 0.0,
-              max_iter: int = 100) -> Result:
+              max_iter: int = 100, hole: bool = False) -> Result:
     """purify with a choice of recursion (HPCP eq. (hpcp3) or PMCP eqs.
     (pm1a)/(pm1b)) and initial guess (PMCP guess, hole-particle mix with alpha,
-    or the alpha search).  Result.alpha is the alpha used (1 = PMCP guess)."""
+    or the alpha search); hole=True purifies I - D0 and returns I - Dbar_p (the
+    history is Dbar's).  Result.alpha is the alpha used (1 = PMCP guess)."""
     H = _f64(H)
     M = H.shape[0]
     D = np.empty((M, M))
@@ -177,8 +178,8 @@ def purify_ex(H: np.ndarray, N: int, emin: float = float("nan"), emax: float = f
     iters = ctypes.c_int()
     scal = np.empty(5)
     st = lib().oracle_purify_ex(M, N, _p(H), emin, emax, METHODS[method], INITS[init], alpha,
-                                delta, tol_ddbar, tol_idem, max_iter, _p(D), _p(hist),
-                                ctypes.byref(iters), _p(scal))
+                                delta, 1 if hole else 0, tol_ddbar, tol_idem, max_iter, _p(D),
+                                _p(hist), ctypes.byref(iters), _p(scal))
     if st == INVALID:
         raise ValueError("invalid purification input")
     n = iters.value

@@ -381,11 +381,13 @@ static double first_c(int64_t M, const double *D)
 /* Full solve with a method (0 HPCP, 1 PMCP) and an initial guess (0 PMCP
  * guess, 1 hole-particle mix with alpha, 2 alpha search with delta).  A
  * hole-particle guess whose c_0 lies outside [0,1] is replaced by the PMCP
- * guess.  scal[0..4]: mu, slope beta, emin, emax, alpha used. */
+ * guess.  hole = 1 purifies Dbar = I - D instead (the alternative the paper
+ * gives before eq. (hpcpguess)); the history is then that of Dbar.
+ * scal[0..4]: mu, slope beta, emin, emax, alpha used. */
 int oracle_purify_ex(int64_t M, int64_t N, const double *H, double emin, double emax,
-                     int method, int init_mode, double alpha, double delta, double tol_ddbar,
-                     double tol_idem, int max_iter, double *D, double *hist, int *iters,
-                     double *scal)
+                     int method, int init_mode, double alpha, double delta, int hole,
+                     double tol_ddbar, double tol_idem, int max_iter, double *D, double *hist,
+                     int *iters, double *scal)
 {
     if (isnan(emin) || isnan(emax)) oracle_gershgorin(M, H, &emin, &emax);
     double sc[3] = {0.0, 0.0, 1.0};
@@ -404,7 +406,15 @@ int oracle_purify_ex(int64_t M, int64_t N, const double *H, double emin, double 
     }
     if (scal) { scal[0] = sc[0]; scal[1] = sc[1]; scal[2] = emin; scal[3] = emax; scal[4] = sc[2]; }
     if (st != ORACLE_OK) { *iters = 0; return st; }
-    return oracle_purify_from_m(M, N, D, method, tol_ddbar, tol_idem, max_iter, hist, iters);
+    if (!hole)
+        return oracle_purify_from_m(M, N, D, method, tol_ddbar, tol_idem, max_iter, hist, iters);
+    /* purify the hole matrix Dbar = I - D (trace M - N) and return I - Dbar */
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = 0; j < M; ++j) D[i * M + j] = (i == j ? 1.0 : 0.0) - D[i * M + j];
+    st = oracle_purify_from_m(M, M - N, D, method, tol_ddbar, tol_idem, max_iter, hist, iters);
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = 0; j < M; ++j) D[i * M + j] = (i == j ? 1.0 : 0.0) - D[i * M + j];
+    return st;
 }
 
 /* Initial guess from (H, N, bounds) followed by the recursion.  NaN bounds

@@ -71,7 +71,7 @@ class Options(ctypes.Structure):
                 ("late_precision", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("switch_ddbar", ctypes.c_double), ("method", ctypes.c_int32),
                 ("init_mode", ctypes.c_int32), ("alpha", ctypes.c_double),
-                ("delta", ctypes.c_double)]
+                ("delta", ctypes.c_double), ("hole", ctypes.c_int32), ("pad2", ctypes.c_int32)]
 
 
 METHODS = {"hpcp": 0, "pmcp": 1}           # the recursion
@@ -178,7 +178,8 @@ class Context:
                  tol_idem: float = 0.0, fold_every: int = 0, profile: bool = False,
                  keep_iterates: bool = False, bwd_precision="fp64", late_precision=None,
                  switch_ddbar: float = 0.0, method: str = "hpcp", init: str = "pmcp",
-                 alpha: float = 0.5, delta: float = 2.0 / 3.0, stream=None):
+                 alpha: float = 0.5, delta: float = 2.0 / 3.0, hole: bool = False,
+                 stream=None):
         L = load_library()
         self._L = L
         self.M = int(M)
@@ -198,6 +199,7 @@ class Context:
         o.init_mode = INITS[init]
         o.alpha = float(alpha)
         o.delta = float(delta)
+        o.hole = 1 if hole else 0
         self.options = o
         self._stream = stream
         h = ctypes.c_void_p()

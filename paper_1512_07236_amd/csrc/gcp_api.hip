@@ -203,6 +203,7 @@ extern "C" int gcp_options_default(gcp_options *opt) {
   opt->init_mode = GCP_INIT_PMCP;
   opt->alpha = 0.5;
   opt->delta = 2.0 / 3.0;
+  opt->hole = 0;
   return GCP_OK;
 }
 
@@ -238,8 +239,8 @@ extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void
   }
   if (o.method < GCP_METHOD_HPCP || o.method > GCP_METHOD_PMCP || o.init_mode < GCP_INIT_PMCP ||
       o.init_mode > GCP_INIT_HP_SEARCH || !(o.alpha >= 0.0 && o.alpha <= 1.0) ||
-      !(o.delta > 0.5 && o.delta < 1.0)) {
-    g_create_error = "gcp_create: method, init_mode, alpha in [0,1] or delta in (1/2,1) invalid";
+      !(o.delta > 0.5 && o.delta < 1.0) || (o.hole != 0 && o.hole != 1)) {
+    g_create_error = "gcp_create: method, init_mode, alpha in [0,1], delta in (1/2,1) or hole invalid";
     return GCP_ERR_INVALID_ARG;
   }
   gcp_ctx *c = new (std::nothrow) gcp_ctx();
@@ -379,7 +380,7 @@ static int reduce(gcp_ctx *c, const double *part, int nslots, int mode, double *
   a.max_iter = c->opt.max_iter;
   a.tol_ddbar = c->opt.tol_ddbar;
   a.tol_idem = c->opt.tol_idem;
-  a.N = (double)c->N;
+  a.N = (double)(c->opt.hole ? c->M - c->N : c->N);   // trace of the purified matrix
   a.sc = c->sc;
   a.hist = c->hist;
   HIPCHK(c, launch_reduce(a, c->stream));
@@ -485,7 +486,9 @@ extern "C" int gcp_init(gcp_ctx *c, const double *H, int64_t ldh, int64_t N, dou
   c->beta_max = bmax;
 
   for (int attempt = 0; attempt < 2; ++attempt) {
-    int st = build_guess(c, H, ldh, theta, beta, mu);
+    // the hole recursion starts from I - D_0 = (1 - theta) I - beta (mu I - H)
+    int st = c->opt.hole ? build_guess(c, H, ldh, 1.0 - theta, -beta, mu)
+                         : build_guess(c, H, ldh, theta, beta, mu);
     if (st != GCP_OK) return st;
     if (c->opt.init_mode == GCP_INIT_PMCP || !(N > 0 && N < c->M) || attempt == 1) break;
     // hole-particle guess: one product gives c_0; Tr(D0 Dbar0) <= 0 or c_0
@@ -706,6 +709,7 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
   oa.ldd = ldd;
   oa.D = D;
   oa.dtype = dtype;
+  oa.hole = c->opt.hole;
   HIPCHK(c, launch_output(prec, oa, c->stream));
   c->hist_rows = iters + 1;
   c->hist_host.assign((size_t)c->hist_rows * GCP_HIST_COLS, NAN);
@@ -723,6 +727,10 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
     res->iters = iters;
     res->t1 = c->sc_host->t1;
     res->t2 = c->sc_host->t2;
+    if (c->opt.hole) {   // Tr D = M - Tr Dbar, Tr D^2 = M - 2 Tr Dbar + Tr Dbar^2
+      res->t1 = (double)c->M - c->sc_host->t1;
+      res->t2 = (double)c->M - 2.0 * c->sc_host->t1 + c->sc_host->t2;
+    }
     res->c_last = iters > 0 ? c->hist_host[(size_t)(iters - 1) * GCP_HIST_COLS + 4] : NAN;
     res->idem = std::sqrt(c->sc_host->omega);
     res->ms_total = std::chrono::duration<double, std::milli>(t_end - t_start).count();
@@ -849,6 +857,13 @@ extern "C" int gcp_backward(gcp_ctx *c, const void *dLdD, int64_t ldg, void *dLd
     const double dbb = -(1.0 - ia.theta) / ((c->mu - c->emin) * (c->mu - c->emin));
     const double dmin = bt <= bb ? dbt : dbb, dmax = bt <= bb ? dbb : dbt;
     ia.dbeta = c->alpha * dmin + (1.0 - c->alpha) * dmax;
+  }
+  ia.sign = 1.0;
+  if (c->opt.hole) {   // Dbar_0 = (1 - theta) I - beta (mu I - H), dL/dDbar = -dL/dD
+    ia.theta = 1.0 - ia.theta;
+    ia.beta = -ia.beta;
+    ia.dbeta = -ia.dbeta;
+    ia.sign = -1.0;
   }
   ia.rows = c->bvec;
   ia.sums = c->bvec + 2 * c->Mp + 1;

@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256) void k_bsum(BwdInitArgs a) {
   }
 }
 
-// dL/dH = -beta G0 + s I (M x M, leading dimension ldh).
+// dL/dH = sign (-beta G0 + s I) (M x M, leading dimension ldh).
 template <int PB>
 __global__ __launch_bounds__(256) void k_bdh(BwdInitArgs a) {
   using TB = typename Enc<PB>::T;
@@ -273,13 +273,14 @@ __global__ __launch_bounds__(256) void k_bdh(BwdInitArgs a) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= a.M) return;
   double s = 0.0;
-  if (a.beta > 0.0) {
+  if (a.beta != 0.0) {
     const double gd = a.sums[0], tr = a.sums[1];
     const double g_muh = (gd - a.theta * tr) / a.beta;   // <G0, mu I - H>
     s = (a.beta * tr + a.dbeta * g_muh) / (double)a.M;
   }
   double x = -a.beta * (double)((const TB *)a.G0)[i * a.Mp + j];
   if (i == j) x += s;
+  x *= a.sign;
   if (a.dtype == GCP_DTYPE_F64)
     ((double *)a.dH)[i * a.ldh + j] = x;
   else

@@ -77,6 +77,7 @@ struct OutArgs {
   int64_t M, Mp, pstride, ldd;
   void *D;
   int dtype;
+  int hole;            // write I - X instead of X
 };
 
 // Adjoint of one update (gcp_backward.hip).  All matrices are Mp x Mp
@@ -102,6 +103,7 @@ struct BwdInitArgs {
   const void *D0;      // D_0 (Mp x Mp)
   int64_t M, Mp, ldh;
   double beta, dbeta, theta;
+  double sign;         // -1 for the hole recursion (dL/dDbar = -dL/dD)
   double *rows;        // 2 Mp scratch: row sums of G0 o D0, diag of G0
   double *sums;        // 2 scalars
   void *dH;            // output, M x M with leading dimension ldh

@@ -936,6 +936,7 @@ __global__ __launch_bounds__(256) void k_output(OutArgs a) {
     for (int q = 0; q < NP; ++q) p[q] = ((const T *)a.planes)[eoff<P>(i, j, q, a.Mp)];
     x = E::dec(p);
   }
+  if (a.hole) x = (i == j ? 1.0 : 0.0) - x;
   if (a.dtype == GCP_DTYPE_F64)
     ((double *)a.D)[i * a.ldd + j] = x;
   else

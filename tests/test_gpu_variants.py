@@ -138,3 +138,38 @@ def test_adjoint_of_the_fixed_alpha_guess_and_unsupported_cases():
             with pytest.raises(gcp.GCPError) as e:
                 ctx.backward(to_gpu(Gp))
             assert e.value.status == gcp.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("method", ["hpcp", "pmcp"])
+def test_hole_purification_matches_oracle(method):
+    """Purifying Dbar = I - D0 (trace M - N) and returning I - Dbar_p."""
+    M = 384
+    w = workloads.spectral(M, 300, 0.1, 74)
+    log(f"[gpu] hole {w.name} {method}")
+    ref = oracle.purify_ex(w.H, w.N, w.emin, w.emax, method=method, hole=True, tol_ddbar=1e-8)
+    D, res, sc = gpu_run(w, w.emin, w.emax, method=method, hole=True, tol_ddbar=1e-8)
+    assert res.status == gcp.OK and res.iters == ref.iters
+    assert np.abs(D - ref.D).max() < 1e-11
+    assert abs(res.t1 - w.N) < 1e-10                        # Tr D of the returned matrix
+    assert np.abs(res.col("t1") - (M - w.N)).max() < 1e-10  # the history is Dbar's
+
+
+def test_hole_purification_mixed_and_adjoint():
+    """FP16X3 hole run against the closed form; the FP64 adjoint of the HPCP
+    hole run equals the particle adjoint (HPCP is hole-particle symmetric)."""
+    M = 384
+    w = workloads.spectral(M, 280, 0.1, 75)
+    ref = oracle.projector_from_spectrum(w.Q, w.lam, w.N)
+    D, res, _ = gpu_run(w, w.emin, w.emax, precision="fp16x3", hole=True, tol_ddbar=1e-6)
+    assert res.status == gcp.OK
+    assert float(np.linalg.norm(D - ref) / np.sqrt(M)) < 1e-6
+    Gp = workloads.sym_gaussian(M, 275)
+    with gcp.Context(M, hole=True, keep_iterates=True, tol_ddbar=1e-6) as ctx:
+        ctx.init(to_gpu(w.H), w.N, w.emin, w.emax)
+        _, r = ctx.purify(raise_on_failure=True)
+        dH, _ = ctx.backward(to_gpu(Gp))
+        dH = dH.cpu().numpy()
+    g = grad.adjoint(w.H, w.N, w.emin, w.emax, r.iters, Gp)
+    err = float(np.abs(dH - g).max() / np.abs(g).max())
+    log(f"  hole adjoint p={r.iters} err={err:.2e}")
+    assert err < 1e-8

@@ -473,3 +473,22 @@ def test_fig3_hole_particle_claims(oracle_lib):
     for th in (0.01, 0.05, 0.95):
         for m in ("hpcp", "pmcp"):
             assert mean(counts(th, m, "search")) < mean(counts(th, m, "pmcp"))
+
+
+@pytest.mark.parametrize("method", ["hpcp", "pmcp"])
+def test_hole_purification_is_particle_purification_of_minus_h(oracle_lib, method):
+    """Purifying Dbar = I - D0 for (H, N) is purifying D for (-H, M - N) with
+    the bounds reflected (the PMCP guess of -H is I - D0), then D = I - Dbar:
+    the same projector.  HPCP is moreover hole-particle symmetric, so its hole
+    run reproduces the particle run itself."""
+    w = workloads.spectral(48, 15, 0.2, 12)
+    M, N = w.M, w.N
+    r = oracle.purify_ex(w.H, N, w.emin, w.emax, method=method, hole=True, tol_ddbar=1e-10)
+    m = oracle.purify_ex(-w.H, M - N, -w.emax, -w.emin, method=method, tol_ddbar=1e-10)
+    assert r.status == m.status == oracle.OK and r.iters == m.iters
+    assert np.abs(r.D - (np.eye(M) - m.D)).max() < 1e-12
+    ref = oracle.projector_from_spectrum(w.Q, w.lam, N)
+    assert np.abs(r.D - ref).max() < 1e-8
+    if method == "hpcp":
+        p = oracle.purify_ex(w.H, N, w.emin, w.emax, tol_ddbar=1e-10)
+        assert p.iters == r.iters and np.abs(p.D - r.D).max() < 1e-12
