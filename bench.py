@@ -345,6 +345,7 @@ def main() -> int:
                    "fold_every": args.fold_every},
         "time_to_solution_ms": t_mixed * 1e3,
         "iters": r0.iters,
+        "iterations_per_s": r0.iters / t_mixed,
         "err": err_m,
         "trace_err": tr_m,
         "meets_1e-6": bool(err_m <= 1e-6 and tr_m <= 1e-10),

@@ -124,7 +124,13 @@ typedef struct {
                               HPCP is hole-particle symmetric (the same iterates up to
                               rounding); PMCP is not.  History rows and gcp_backward's
                               kept iterates are those of Dbar; result t1/t2 are of D. */
-    int32_t pad2;
+    int32_t checkpoint_every; /* with keep_iterates: 0 or 1 (default) keeps every iterate;
+                              k >= 2 keeps only the state of every k-th iterate (operand
+                              planes and FP64 diagonals) and gcp_backward recomputes each
+                              segment of k updates from it with the forward kernels
+                              (bitwise the same iterates), storing k iterates at a time:
+                              memory p/k + k matrices instead of p, for two extra
+                              products per update in the backward. */
 } gcp_options;
 
 enum { GCP_METHOD_HPCP = 0, GCP_METHOD_PMCP = 1 };

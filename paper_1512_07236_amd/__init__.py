@@ -71,7 +71,8 @@ class Options(ctypes.Structure):
                 ("late_precision", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("switch_ddbar", ctypes.c_double), ("method", ctypes.c_int32),
                 ("init_mode", ctypes.c_int32), ("alpha", ctypes.c_double),
-                ("delta", ctypes.c_double), ("hole", ctypes.c_int32), ("pad2", ctypes.c_int32)]
+                ("delta", ctypes.c_double), ("hole", ctypes.c_int32),
+                ("checkpoint_every", ctypes.c_int32)]
 
 
 METHODS = {"hpcp": 0, "pmcp": 1}           # the recursion
@@ -179,7 +180,7 @@ class Context:
                  keep_iterates: bool = False, bwd_precision="fp64", late_precision=None,
                  switch_ddbar: float = 0.0, method: str = "hpcp", init: str = "pmcp",
                  alpha: float = 0.5, delta: float = 2.0 / 3.0, hole: bool = False,
-                 stream=None):
+                 checkpoint_every: int = 0, stream=None):
         L = load_library()
         self._L = L
         self.M = int(M)
@@ -200,6 +201,7 @@ class Context:
         o.alpha = float(alpha)
         o.delta = float(delta)
         o.hole = 1 if hole else 0
+        o.checkpoint_every = int(checkpoint_every)
         self.options = o
         self._stream = stream
         h = ctypes.c_void_p()

@@ -92,8 +92,17 @@ struct gcp_ctx {
   double t1_0 = NAN, t2_0 = NAN;
   void *D0p = nullptr;      // copy of the D_0 planes so purify can be re-run
   double *dg0 = nullptr, *rD0 = nullptr, *d20 = nullptr;
-  // reverse mode: stored iterates D_0 .. D_{p-1} (adjoint type, Mp x Mp each)
+  // reverse mode: stored iterates D_0 .. D_{p-1} (adjoint type, Mp x Mp each),
+  // or with checkpoint_every = k >= 2 the forward state at every k-th step
+  // (operand planes + dg, rD, d2) and k recomputed iterates at a time
   std::vector<void *> slots;
+  struct Ckpt {
+    void *planes = nullptr;
+    double *vec = nullptr;   // dg, rD, d2 (3 Mp)
+    int pi = 0;              // encoding index (precision schedule)
+  };
+  std::vector<Ckpt> ckpts;
+  int n_switch = -1;         // update at which the schedule switched encodings
   int bwd_p = -1;           // updates covered by the stored iterates (-1: none)
   void *bG[2] = {nullptr, nullptr};
   void *bX2 = nullptr, *bAT = nullptr, *bCT = nullptr;
@@ -141,6 +150,11 @@ static void free_all(gcp_ctx *c) {
   for (void *p : c->slots)
     if (p) (void)hipFree(p);
   c->slots.clear();
+  for (auto &k : c->ckpts) {
+    if (k.planes) (void)hipFree(k.planes);
+    if (k.vec) (void)hipFree(k.vec);
+  }
+  c->ckpts.clear();
   if (c->sc_host) (void)hipHostFree(c->sc_host);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   c->events.clear();
@@ -204,6 +218,7 @@ extern "C" int gcp_options_default(gcp_options *opt) {
   opt->alpha = 0.5;
   opt->delta = 2.0 / 3.0;
   opt->hole = 0;
+  opt->checkpoint_every = 0;
   return GCP_OK;
 }
 
@@ -239,8 +254,11 @@ extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void
   }
   if (o.method < GCP_METHOD_HPCP || o.method > GCP_METHOD_PMCP || o.init_mode < GCP_INIT_PMCP ||
       o.init_mode > GCP_INIT_HP_SEARCH || !(o.alpha >= 0.0 && o.alpha <= 1.0) ||
-      !(o.delta > 0.5 && o.delta < 1.0) || (o.hole != 0 && o.hole != 1)) {
-    g_create_error = "gcp_create: method, init_mode, alpha in [0,1], delta in (1/2,1) or hole invalid";
+      !(o.delta > 0.5 && o.delta < 1.0) || (o.hole != 0 && o.hole != 1) ||
+      o.checkpoint_every < 0) {
+    g_create_error =
+        "gcp_create: method, init_mode, alpha in [0,1], delta in (1/2,1), hole or checkpoint_every "
+        "invalid";
     return GCP_ERR_INVALID_ARG;
   }
   gcp_ctx *c = new (std::nothrow) gcp_ctx();
@@ -585,6 +603,132 @@ static int store_iterate(gcp_ctx *c, int n, int k, int prec) {
   return GCP_OK;
 }
 
+// Launch accounting of one solve (events when profiling, issued MFMA flops).
+struct LaunchLog {
+  bool prof = false;
+  int n = 0;
+  double mfma_flops = 0.0;
+};
+
+// One product launch in encoding pc[pi].
+static int run_product(gcp_ctx *c, GemmArgs &g, int pi, LaunchLog *log) {
+  const gcp_ctx::PrecCfg &q = c->pc[pi];
+  g.fold = q.fold;
+  g.nfull = q.nfull;
+  g.nsplit = q.nsplit;
+  const bool ev = log && log->prof && 2 * log->n + 1 < (int)c->events.size();
+  if (ev) HIPCHK(c, hipEventRecord(c->events[2 * log->n], c->stream));
+  HIPCHK(c, launch_gemm(q.prec, g, c->stream));
+  if (ev) HIPCHK(c, hipEventRecord(c->events[2 * log->n + 1], c->stream));
+  if (log) {
+    ++log->n;
+    log->mfma_flops +=
+        (double)c->ntiles * 2.0 * 128.0 * 128.0 * (double)c->Mp * (double)products(q.prec);
+  }
+  return GCP_OK;
+}
+
+// K1 of update n on the iterate in buffer k: X2 = D D and the scalar step.
+static int step_k1(gcp_ctx *c, GemmArgs &g, int pi, int k, int n, LaunchLog *log) {
+  g.mode = 0;
+  g.A = c->Dp[k];
+  g.B = c->Dp[k];
+  g.out = c->X2p;
+  g.dg = c->dg[k];
+  g.rD = c->rD[k];
+  g.d2 = c->d2[k];
+  int st = run_product(c, g, pi, log);
+  if (st != GCP_OK) return st;
+  return reduce(c, c->part, c->nt, 1, c->d3, nullptr, c->tpart, c->pc[pi].ntpart, n);
+}
+
+// K2 of update n: D_{n+1} into buffer 1 - k.
+static int step_k2(gcp_ctx *c, GemmArgs &g, int pi, int k, int n, LaunchLog *log) {
+  g.mode = 1;
+  g.A = c->X2p;
+  g.B = c->Dp[k];
+  g.out = c->Dp[1 - k];
+  g.dg_new = c->dg[1 - k];
+  g.rD_new = c->rD[1 - k];
+  int st = run_product(c, g, pi, log);
+  if (st != GCP_OK) return st;
+  return reduce(c, c->part, c->nt, 2, c->d2[1 - k], c->dg[1 - k], c->tpart, c->pc[pi].ntpart, n);
+}
+
+// Precision schedule: re-encode D_n (buffer k) and X2 = D_n^2 in pc[1]; the
+// FP64 diagonals (dg, d2, d3) and c_n are unchanged, the residuals of the new
+// encoding replace rD and s2.
+static int switch_precision(gcp_ctx *c, int k) {
+  const int pa = c->pc[0].prec, pb = c->pc[1].prec;
+  HIPCHK(c, launch_convert(pa, pb, c->Dp[k], c->dg[k], c->Xc, c->rD[k], c->Mp, c->stream));
+  std::swap(c->Dp[k], c->Xc);
+  HIPCHK(c, launch_convert(pa, pb, c->X2p, c->d2[k], c->Xc, c->s2, c->Mp, c->stream));
+  std::swap(c->X2p, c->Xc);
+  return GCP_OK;
+}
+
+// Checkpoint j: the forward state that K1 of update j * checkpoint_every reads.
+static int save_checkpoint(gcp_ctx *c, int j, int k, int pi) {
+  const size_t vec = (size_t)c->Mp * sizeof(double);
+  while ((int)c->ckpts.size() <= j) {
+    gcp_ctx::Ckpt q;
+    if (hipMalloc(&q.planes, plane_bytes(c)) != hipSuccess ||
+        hipMalloc((void **)&q.vec, 3 * vec) != hipSuccess) {
+      if (q.planes) (void)hipFree(q.planes);
+      c->err = "gcp_purify: out of device memory for the checkpoints kept for gcp_backward";
+      return GCP_ERR_NO_MEMORY;
+    }
+    c->ckpts.push_back(q);
+  }
+  gcp_ctx::Ckpt &q = c->ckpts[j];
+  q.pi = pi;
+  HIPCHK(c, hipMemcpyAsync(q.planes, c->Dp[k], plane_bytes(c), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(q.vec, c->dg[k], vec, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(q.vec + c->Mp, c->rD[k], vec, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(q.vec + 2 * c->Mp, c->d2[k], vec, hipMemcpyDeviceToDevice, c->stream));
+  return GCP_OK;
+}
+
+// Recompute updates [n0, n1) from checkpoint n0 / checkpoint_every, keeping
+// D_n as slot n - n0 (the forward's kernels, launch configuration and
+// decisions: bitwise the iterates of gcp_purify).
+static int recompute_segment(gcp_ctx *c, int n0, int n1) {
+  const size_t vec = (size_t)c->Mp * sizeof(double);
+  const gcp_ctx::Ckpt &q = c->ckpts[n0 / c->opt.checkpoint_every];
+  HIPCHK(c, hipMemcpyAsync(c->Dp[0], q.planes, plane_bytes(c), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->dg[0], q.vec, vec, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->rD[0], q.vec + c->Mp, vec, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d2[0], q.vec + 2 * c->Mp, vec, hipMemcpyDeviceToDevice, c->stream));
+  Scalars s0{};   // traces of D_{n0}, as K1's reduction expects them
+  s0.t1 = c->hist_host[(size_t)n0 * GCP_HIST_COLS + 1];
+  s0.t2 = c->hist_host[(size_t)n0 * GCP_HIST_COLS + 2];
+  *c->sc_host = s0;
+  HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
+  int pi = q.pi, k = 0;
+  if (n0 == n1) {   // no update applied (p = 0): keep D_{n0} itself
+    int st = store_iterate(c, 0, 0, c->pc[pi].prec);
+    if (st != GCP_OK) return st;
+  }
+  GemmArgs g{};
+  setup_gemm(c, g, pi);
+  for (int n = n0; n < n1; ++n) {
+    int st = step_k1(c, g, pi, k, n, nullptr);
+    if (st != GCP_OK) return st;
+    if (n == c->n_switch) {
+      st = switch_precision(c, k);
+      if (st != GCP_OK) return st;
+      pi = 1;
+    }
+    st = store_iterate(c, n - n0, k, c->pc[pi].prec);
+    if (st != GCP_OK) return st;
+    st = step_k2(c, g, pi, k, n, nullptr);
+    if (st != GCP_OK) return st;
+    k = 1 - k;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));   // the host copy of the scalars is reused
+  return GCP_OK;
+}
+
 extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_result *res) {
   if (!c) return GCP_ERR_INVALID_ARG;
   if (!c->inited) {
@@ -616,7 +760,7 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
 
   const bool keep = c->opt.keep_iterates != 0;
   c->bwd_p = -1;
-  if (keep) {
+  if (keep && c->opt.checkpoint_every < 2) {
     const int st = store_iterate(c, 0, 0, prec);
     if (st != GCP_OK) return st;
   }
@@ -630,38 +774,21 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
       c->events.push_back(e);
     }
   }
-  int nlaunch = 0;
-  double mfma_flops = 0.0;
+  LaunchLog lg;
+  lg.prof = prof;
   GemmArgs g{};
-  auto gemm = [&](GemmArgs &ga) -> int {
-    const gcp_ctx::PrecCfg &q = c->pc[pi];
-    ga.fold = q.fold;
-    ga.nfull = q.nfull;
-    ga.nsplit = q.nsplit;
-    if (prof) HIPCHK(c, hipEventRecord(c->events[2 * nlaunch], c->stream));
-    HIPCHK(c, launch_gemm(prec, ga, c->stream));
-    if (prof) HIPCHK(c, hipEventRecord(c->events[2 * nlaunch + 1], c->stream));
-    ++nlaunch;
-    mfma_flops += (double)c->ntiles * 2.0 * 128.0 * 128.0 * (double)c->Mp * (double)products(prec);
-    return GCP_OK;
-  };
-
   setup_gemm(c, g, 0);
+  const int ck = keep && c->opt.checkpoint_every >= 2 ? c->opt.checkpoint_every : 0;
+  c->n_switch = -1;
 
   int status = 0, n = 0;
   for (;; ++n) {
     const int k = c->cur;
-    // K1: X2 = D D
-    g.mode = 0;
-    g.A = c->Dp[k];
-    g.B = c->Dp[k];
-    g.out = c->X2p;
-    g.dg = c->dg[k];
-    g.rD = c->rD[k];
-    g.d2 = c->d2[k];
-    int st = gemm(g);
-    if (st != GCP_OK) return st;
-    st = reduce(c, c->part, c->nt, 1, c->d3, nullptr, c->tpart, c->pc[pi].ntpart, n);
+    if (ck && n % ck == 0) {
+      int st = save_checkpoint(c, n / ck, k, pi);
+      if (st != GCP_OK) return st;
+    }
+    int st = step_k1(c, g, pi, k, n, &lg);
     if (st != GCP_OK) return st;
     HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -669,31 +796,17 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
     if (status != 0) break;
     if (pi == 0 && c->nprec > 1 &&
         std::fabs(c->sc_host->t1 - c->sc_host->t2) <= c->opt.switch_ddbar) {
-      // precision schedule: re-encode D_n and X2 = D_n^2 for the rest of the
-      // solve; the FP64 diagonals (dg, d2, d3) and c_n are unchanged, the
-      // residuals of the new encoding replace rD and s2
-      const int pn = c->pc[1].prec;
-      HIPCHK(c, launch_convert(prec, pn, c->Dp[k], c->dg[k], c->Xc, c->rD[k], c->Mp, c->stream));
-      std::swap(c->Dp[k], c->Xc);
-      HIPCHK(c, launch_convert(prec, pn, c->X2p, c->d2[k], c->Xc, c->s2, c->Mp, c->stream));
-      std::swap(c->X2p, c->Xc);
+      st = switch_precision(c, k);
+      if (st != GCP_OK) return st;
       pi = 1;
-      prec = pn;
+      prec = c->pc[1].prec;
+      c->n_switch = n;
     }
-    if (keep && n > 0) {
+    if (keep && !ck && n > 0) {
       st = store_iterate(c, n, k, prec);
       if (st != GCP_OK) return st;
     }
-    // K2: D_{n+1} = (1 - 2c) D + (2 + 2c) X2 - 2 X2 D
-    g.mode = 1;
-    g.A = c->X2p;
-    g.B = c->Dp[k];
-    g.out = c->Dp[1 - k];
-    g.dg_new = c->dg[1 - k];
-    g.rD_new = c->rD[1 - k];
-    st = gemm(g);
-    if (st != GCP_OK) return st;
-    st = reduce(c, c->part, c->nt, 2, c->d2[1 - k], c->dg[1 - k], c->tpart, c->pc[pi].ntpart, n);
+    st = step_k2(c, g, pi, k, n, &lg);
     if (st != GCP_OK) return st;
     c->cur = 1 - k;
   }
@@ -734,13 +847,13 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
     res->c_last = iters > 0 ? c->hist_host[(size_t)(iters - 1) * GCP_HIST_COLS + 4] : NAN;
     res->idem = std::sqrt(c->sc_host->omega);
     res->ms_total = std::chrono::duration<double, std::milli>(t_end - t_start).count();
-    res->gemm_launches = nlaunch;
+    res->gemm_launches = lg.n;
     const double Md = (double)c->M;
-    res->gemm_flops = (double)nlaunch * Md * Md * (Md + 1.0);
-    res->mfma_flops = mfma_flops;
+    res->gemm_flops = (double)lg.n * Md * Md * (Md + 1.0);
+    res->mfma_flops = lg.mfma_flops;
     double ms = 0.0;
     if (prof) {
-      for (int k = 0; k < nlaunch; ++k) {
+      for (int k = 0; k < lg.n; ++k) {
         float t = 0.f;
         HIPCHK(c, hipEventElapsedTime(&t, c->events[2 * k], c->events[2 * k + 1]));
         ms += t;
@@ -812,10 +925,23 @@ extern "C" int gcp_backward(gcp_ctx *c, const void *dLdD, int64_t ldg, void *dLd
   a.CT = c->bCT;
   a.kappa = kappa;
   a.tpart = c->btpart;
+  // iterates: all kept (slot n = D_n), or recomputed segment by segment from
+  // the checkpoints (slot n - n0 = D_n), last segment first
+  const int ck = c->opt.checkpoint_every >= 2 ? c->opt.checkpoint_every : 0;
+  int n0 = ck ? (p > 0 ? (p - 1) / ck * ck : 0) : 0;
+  if (ck) {
+    int st = recompute_segment(c, n0, p);
+    if (st != GCP_OK) return st;
+  }
   for (int n = p - 1; n >= 0; --n) {
+    if (ck && n < n0) {
+      n0 -= ck;
+      int st = recompute_segment(c, n0, n0 + ck);
+      if (st != GCP_OK) return st;
+    }
     const double *h = c->hist_host.data() + (size_t)n * GCP_HIST_COLS;
     const double cn = h[4], t12 = h[1] - h[2];
-    a.D = c->slots[n];
+    a.D = c->slots[n - n0];
     a.G = c->bG[cur];
     a.a = 1.0 - 2.0 * cn;
     a.b = 2.0 + 2.0 * cn;

@@ -45,14 +45,14 @@ def test_struct_layout_matches_c_compiler(tmp_path):
         'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gcp_options),'
         ' sizeof(gcp_verify_result), offsetof(gcp_verify_result, ms),'
         ' sizeof(gcp_result), offsetof(gcp_options, fold_every),'
-        ' offsetof(gcp_options, hole), offsetof(gcp_result, gemm_launches),'
+        ' offsetof(gcp_options, checkpoint_every), offsetof(gcp_result, gemm_launches),'
         ' offsetof(gcp_result, mfma_flops));return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     assert got == [ctypes.sizeof(gcp.Options), ctypes.sizeof(gcp.CVerify), gcp.CVerify.ms.offset,
                    ctypes.sizeof(gcp.CResult),
-                   gcp.Options.fold_every.offset, gcp.Options.hole.offset,
+                   gcp.Options.fold_every.offset, gcp.Options.checkpoint_every.offset,
                    gcp.CResult.gemm_launches.offset, gcp.CResult.mfma_flops.offset]
 
 
@@ -61,8 +61,8 @@ def test_options_default(lib):
     o = gcp.default_options()
     assert (o.precision, o.max_iter, o.tol_ddbar, o.tol_idem, o.fold_every, o.profile,
             o.keep_iterates, o.bwd_precision, o.late_precision, o.switch_ddbar, o.method,
-            o.init_mode, o.alpha, o.delta, o.hole) == \
-        (0, 100, 1e-6, 0.0, 0, 0, 0, 0, -1, 0.0, 0, 0, 0.5, 2.0 / 3.0, 0)
+            o.init_mode, o.alpha, o.delta, o.hole, o.checkpoint_every) == \
+        (0, 100, 1e-6, 0.0, 0, 0, 0, 0, -1, 0.0, 0, 0, 0.5, 2.0 / 3.0, 0, 0)
     assert lib.gcp_options_default(None) == gcp.ERR_INVALID_ARG
 
 
@@ -84,7 +84,7 @@ def test_create_rejects_bad_arguments_before_touching_the_device(lib):
         assert lib.gcp_create(ctypes.byref(h), 16, ctypes.byref(o), None) == gcp.ERR_INVALID_ARG
         assert b"bwd_precision" in lib.gcp_last_error(None)
     for field, bad in (("method", 2), ("init_mode", 3), ("alpha", 1.5), ("delta", 0.4),
-                       ("hole", 2)):
+                       ("hole", 2), ("checkpoint_every", -1)):
         o = gcp.default_options()
         setattr(o, field, bad)
         assert lib.gcp_create(ctypes.byref(h), 16, ctypes.byref(o), None) == gcp.ERR_INVALID_ARG
