@@ -278,7 +278,9 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
   static_assert((PD - 1) * LPS <= 63, "vmcnt range");
   constexpr int EPLD = TILE + 4;                 // epilogue row pitch (floats)
   constexpr int WPT = NW16 / 2;                  // waves per tile in the epilogue
-  constexpr int EPI = (2 * TILE * EPLD * 4 + (2 + 2 * WPT) * TILE * 8 + 2 * WPT * 8) / 2;   // halves
+  constexpr int EVEC = 5 * TILE + BR;            // FP64 side vectors staged for the epilogue
+  constexpr int EPI =
+      (2 * TILE * EPLD * 4 + (2 + 2 * WPT) * TILE * 8 + 2 * WPT * 8 + EVEC * 8) / 2;   // halves
   constexpr int SMEM = NBUF * STAGE > EPI ? NBUF * STAGE : EPI;
   __shared__ __attribute__((aligned(16))) T smem[SMEM];
 
@@ -307,14 +309,16 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
   const int tj = cpair * PAIR_COLS + h;
   const bool valid = tj >= ti;
 
-  // 128-byte rows: the 8 chunks of stage row R sit at slots c ^ s(R),
-  // s(R) = (R ^ (R >> 3)) % 8, so the rows read by an MFMA fragment fall on
-  // distinct banks whether the LDS serves 8 lanes of 16 B per cycle (32
-  // banks) or 16 lanes (64 banks).  64-byte rows (three planes): 4 chunks at
-  // slots c ^ ((R >> 1) ^ (R >> 3)) % 4.  Global data goes straight to LDS
+  // 128-byte rows: the 8 chunks of stage row R sit at slots c ^ (R % 8), so
+  // the 16 rows an MFMA fragment read touches cover every slot twice, with
+  // the two rows of a slot of opposite parity.  Measured on gfx950 with the
+  // fragment pattern alone: no LDS bank conflicts (SQ_LDS_BANK_CONFLICT = 0)
+  // and 176 B/clk per CU, against 2-way conflicts and 117 B/clk for the slot
+  // c ^ ((R ^ (R >> 3)) % 8).  64-byte rows (three planes): 4 chunks at slots
+  // c ^ ((R >> 1) ^ (R >> 3)) % 4.  Global data goes straight to LDS
   // (global_load_lds, 16 B per lane; one wave instruction fills 8 or 16
   // contiguous rows).
-  auto swz = [](int R) { return R128 ? ((R ^ (R >> 3)) & 7) : (((R >> 1) ^ (R >> 3)) & 3); };
+  auto swz = [](int R) { return R128 ? (R & 7) : (((R >> 1) ^ (R >> 3)) & 3); };
   auto issue = [&](int kt, int buf) {
     T *st = smem + buf * STAGE;
 #pragma unroll
@@ -468,6 +472,27 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
   double *rp = (double *)(V + 2 * TILE * EPLD);   // [2 tiles][128] row sums
   double *cpart = rp + 2 * TILE;                  // [2 tiles][WPT waves][128] column sums
   double *tp = cpart + 2 * WPT * TILE;            // [2 tiles][WPT waves] tile sums
+  // The FP64 side vectors of the block's rows (rD, s2, dg, d2, d3) and
+  // columns (rD) are staged in LDS: read per element from global memory they
+  // would each wait for the stores before them (the compiler cannot tell
+  // them from the output), one memory round trip per element.
+  double *vrow = tp + 2 * WPT;                    // [5][128]
+  double *vcol = vrow + 5 * TILE;                 // [256]
+  for (int q = tid; q < EVEC; q += NTH16) {
+    if (q < 5 * TILE) {
+      const int k = q / TILE;
+      const int64_t i = arow0 + q % TILE;
+      double v = 0.0;
+      if (k == 0) v = g.rD[i];
+      else if (k == 1) v = g.mode == 1 ? g.s2[i] : 0.0;
+      else if (k == 2) v = g.dg[i];
+      else if (k == 3) v = g.d2[i];
+      else v = g.mode == 1 ? g.d3[i] : 0.0;
+      vrow[q] = v;
+    } else {
+      vcol[q - 5 * TILE] = g.rD[brow0 + q - 5 * TILE];
+    }
+  }
   if (valid) {
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
@@ -521,11 +546,11 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
         if (g.mode == 0) {
           double Dm, x2;
           if (i == j) {
-            Dm = g.dg[i];
-            x2 = g.d2[i];
+            Dm = vrow[2 * TILE + br * 8 + r];
+            x2 = vrow[3 * TILE + br * 8 + r];
           } else {
             Dm = E::dec(dp);
-            x2 = v + Dm * (g.rD[i] + g.rD[j]);
+            x2 = v + Dm * (vrow[br * 8 + r] + vcol[th * TILE + bc * 8 + e]);
           }
           E::enc(x2, op);
           const double x2m = (i == j) ? x2 : E::dec(op);
@@ -535,15 +560,15 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
         } else {
           double Dm, dn;
           if (i == j) {
-            Dm = g.dg[i];
-            dn = a_coef * Dm + b_coef * g.d2[i] + e_coef * g.d3[i];
+            Dm = vrow[2 * TILE + br * 8 + r];
+            dn = a_coef * Dm + b_coef * vrow[3 * TILE + br * 8 + r] + e_coef * vrow[4 * TILE + br * 8 + r];
           } else {
             T xp[NP];
 #pragma unroll
             for (int p = 0; p < NP; ++p) xp[p] = (uint16_t)(xv[p][e >> 1] >> (16 * (e & 1)));
             Dm = E::dec(dp);
             const double X2m = E::dec(xp);
-            const double x3 = v + X2m * g.rD[j] + g.s2[i] * Dm;
+            const double x3 = v + X2m * vcol[th * TILE + bc * 8 + e] + vrow[TILE + br * 8 + r] * Dm;
             dn = a_coef * Dm + b_coef * X2m + e_coef * x3;
           }
           E::enc(dn, op);

@@ -329,3 +329,18 @@ def test_schedule_switch(early, late, switch, err_lo, err_hi):
     assert err_lo <= err < err_hi
     if late == "fp64":
         assert res.idem < 1e-9
+
+
+@pytest.mark.parametrize("precision,tol_ddbar,err_tol", [("fp64", 1e-9, 1e-10),
+                                                          ("fp32", 1e-5, 2e-6)])
+def test_full_size_spectral_4096_fp64_vs_fp32(precision, tol_ddbar, err_tol):
+    """M = 4096, N = 2048, gap 0.1: FP64 to the oracle's accuracy, FP32 to its
+    rounding (about 2^-24 per product over 2p products)."""
+    w = workloads.config(2)
+    ref = oracle.projector_from_spectrum(w.Q, w.lam, w.N)
+    D, res = run_gpu(w, precision, tol_ddbar=tol_ddbar)
+    err = rel_err(D, ref)
+    log(f"  {precision}: iters={res.iters} err={err:.3e} ms={res.ms_total:.1f}")
+    assert res.status == gcp.OK
+    assert np.abs(res.col("t1") - w.N).max() < 1e-10
+    assert err < err_tol
