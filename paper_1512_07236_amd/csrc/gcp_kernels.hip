@@ -795,31 +795,28 @@ __global__ __launch_bounds__(256) void k_hdev_sum(const double *part, int n, dou
 // ------------------------------------------------------------ initial guess
 // D0 = theta I + beta (mu I - (H + H^T)/2) over 64 x 64 tiles of the padded
 // matrix; writes the operand planes, the FP64 diagonal (dg, rD) and row sums
-// of D0 o D0 into part[tile column][row] (the diagonal of D0^2).
+// of D0 o D0 into part[tile column][row] (the diagonal of D0^2).  One block
+// per mirrored tile pair (I, J), (J, I) with I <= J: each tile of H is read
+// once, and (H_ij + H_ji)/2 is the same sum in both output tiles, so D0 is
+// exactly symmetric.
+
+// Output tile (I, J) of the pair: hv[q] = H[I + r][J + lane] from the
+// block's own load (r = 4q + wave), tr[c][r] = H[J + c][I + r] from LDS.
 template <int P>
-__global__ __launch_bounds__(256) void k_init(InitArgs a) {
+__device__ __forceinline__ void init_tile(const InitArgs &a, int64_t I, int64_t J,
+                                          const double (&hv)[16],
+                                          const double (*tr)[65], int wave, int lane) {
   using E = Enc<P>;
   using T = typename E::T;
   constexpr int NP = E::NP;
-  __shared__ double hs[64][65], ht[64][65];
-  const int64_t I = (int64_t)blockIdx.y * 64, J = (int64_t)blockIdx.x * 64;
-  const int tid = threadIdx.x, row = tid >> 2, c0 = (tid & 3) * 16;
-  // hs[row][c] = H[I+row][J+c], ht[row][c] = H[J+row][I+c]
-#pragma unroll 4
-  for (int c = 0; c < 16; ++c) {
-    const int64_t gi = I + row, gj = J + c0 + c;
-    hs[row][c0 + c] = (gi < a.M && gj < a.M) ? a.H[gi * a.ldh + gj] : 0.0;
-    const int64_t ti = J + row, tj = I + c0 + c;
-    ht[row][c0 + c] = (ti < a.M && tj < a.M) ? a.H[ti * a.ldh + tj] : 0.0;
-  }
-  __syncthreads();
   T *__restrict__ Og = (T *)a.out;
-  double rsum = 0.0;
-  for (int c = 0; c < 16; ++c) {
-    const int64_t i = I + row, j = J + c0 + c;
+#pragma unroll 2
+  for (int q = 0; q < 16; ++q) {
+    const int r = 4 * q + wave;
+    const int64_t i = I + r, j = J + lane;
     double x = 0.0;
     if (i < a.M && j < a.M) {
-      const double h = 0.5 * (hs[row][c0 + c] + ht[c0 + c][row]);
+      const double h = 0.5 * (hv[q] + tr[lane][r]);
       x = -a.beta * h;
       if (i == j) x += a.theta + a.beta * a.mu;
     }
@@ -832,11 +829,50 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a) {
       a.dg[i] = x;
       a.rD[i] = x - E::dec(op);
     }
-    rsum += xm * xm;
+    // row sum of D0 o D0 over the tile's 64 columns (fixed order)
+    double rs = xm * xm;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) rs += __shfl_xor(rs, m, 64);
+    if (lane == 0) a.part[(J >> 6) * a.Mp + i] = rs;
   }
-  rsum += __shfl_xor(rsum, 1, 64);
-  rsum += __shfl_xor(rsum, 2, 64);
-  if ((tid & 3) == 0) a.part[(int64_t)blockIdx.x * a.Mp + I + row] = rsum;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_init(InitArgs a) {
+  __shared__ double ta[64][65], tb[64][65];
+  // block L -> (u, v), v <= u, of the row-major lower triangle
+  const int64_t L = blockIdx.x;
+  int64_t u = (int64_t)((sqrt(8.0 * (double)L + 1.0) - 1.0) * 0.5);
+  while (u * (u + 1) / 2 > L) --u;
+  while ((u + 1) * (u + 2) / 2 <= L) ++u;
+  const int64_t v = L - u * (u + 1) / 2;
+  const int64_t I = v * 64, J = u * 64;
+  const bool diag = u == v;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // ha[q] = H[I+r][J+lane], hb[q] = H[J+r][I+lane]; a wave reads 64
+  // consecutive elements (512 bytes) of one row per load
+  double ha[16], hb[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int r = 4 * q + wave;
+    const int64_t gi = I + r, gj = J + lane;
+    ha[q] = (gi < a.M && gj < a.M) ? a.H[gi * a.ldh + gj] : 0.0;
+    const int64_t ti = J + r, tj = I + lane;
+    hb[q] = (!diag && ti < a.M && tj < a.M) ? a.H[ti * a.ldh + tj] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int r = 4 * q + wave;
+    ta[r][lane] = ha[q];
+    tb[r][lane] = hb[q];
+  }
+  __syncthreads();
+  if (diag) {
+    init_tile<P>(a, I, J, ha, ta, wave, lane);
+  } else {
+    init_tile<P>(a, I, J, ha, tb, wave, lane);
+    init_tile<P>(a, J, I, hb, ta, wave, lane);
+  }
 }
 
 // -------------------------------------------------------------- reductions
@@ -1055,7 +1091,8 @@ hipError_t launch_gemm(int prec, const GemmArgs &g, hipStream_t st) {
 }
 
 hipError_t launch_init(int prec, const InitArgs &a, hipStream_t st) {
-  const dim3 grid((unsigned)(a.Mp / 64), (unsigned)(a.Mp / 64));
+  const int64_t nt = a.Mp / 64;
+  const dim3 grid((unsigned)(nt * (nt + 1) / 2));
   switch (prec) {
     case GCP_FP64: k_init<GCP_FP64><<<grid, 256, 0, st>>>(a); break;
     case GCP_FP32: k_init<GCP_FP32><<<grid, 256, 0, st>>>(a); break;

@@ -270,11 +270,20 @@ def test_full_size_spectral_8192(config3, precision, tol_ddbar, err_tol):
     n = min(res.iters, s["iters"])
     ddbar = (res.col("t1") - res.col("t2"))[:n]
     # c_n = (T2 - T3)/(T1 - T2): an absolute error e in the traces of the
-    # iterate moves c_n by about e/(T1 - T2).  FP64: e ~ 1e-12 (summation);
-    # the split encodings carry ~2^-22 relative error per element, which
-    # measured as e ~ 8e-7 at M = 8192, N = 3000 (bound: 1e-5).
-    ctol, cnum = (1e-11, 1e-12) if precision == "fp64" else (1e-4, 1e-5)
-    assert np.all(np.abs(res.col("c")[:n] - s["c"][:n]) <= ctol + cnum / np.abs(ddbar))
+    # iterate moves c_n by about e/(T1 - T2).  FP64: the traces (~N = 3000)
+    # are tree sums over 8192 rows; the top levels dominate, each adding
+    # ~2^-53 x 3000 x 2^(-k/2) at depth k, ~1.1e-12 RMS per trace and
+    # ~1.5e-12 for the difference, so e = 4e-12 (3 sigma); measured e up
+    # to 1.6e-12 and |Tr D - N| = 3.6e-12 at this size.  The split
+    # encodings carry ~2^-22 relative error per element, which measured
+    # as e ~ 8e-7 (bound: 1e-5).
+    ctol, cnum = (1e-11, 4e-12) if precision == "fp64" else (1e-4, 1e-5)
+    dc = np.abs(res.col("c")[:n] - s["c"][:n])
+    ratio = dc / (ctol + cnum / np.abs(ddbar))
+    k = int(np.argmax(ratio))
+    log(f"  c_n: worst n={k} dc={dc[k]:.3e} ddbar={ddbar[k]:.3e} ratio={ratio[k]:.3f}; "
+        + " ".join(f"{x:.2e}" for x in dc * np.abs(ddbar)))
+    assert np.all(ratio <= 1.0)
     assert abs(res.iters - s["iters"]) <= (0 if precision == "fp64" else 1)
 
 
