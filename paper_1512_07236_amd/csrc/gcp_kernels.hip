@@ -350,6 +350,9 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
       return *(const v4u *)(st + (x * (AR + BR) + R) * KT + (lg ^ swz(R)) * 8);
   };
   constexpr int NX = R128 ? 2 : NP;              // fragment groups per stage row
+  // two wave groups half a stage apart (below); the three-plane encodings
+  // keep the plain loop (their fragments would not fit in the registers)
+  constexpr bool PING = R128;
 
   v4f acc[4][NBJ], tot[4][NBJ];
 #pragma unroll
@@ -368,56 +371,103 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
   constexpr int QA[2] = {0, 1};
 
   const int fold = g.fold;   // >= 1 (resolved on the host)
-  // Waves of a tile below the diagonal run the same instruction stream (their
-  // results are discarded): the loop body stays branch-free, which keeps the
-  // accumulators in place across iterations.
-#pragma unroll
-  for (int s0 = 0; s0 < PD; ++s0)
-    if (s0 < nk) issue(s0, s0);
-  for (int k0 = 0; k0 < nk; k0 += fold) {
-    const int k1 = min(nk, k0 + fold);
-    for (int kt = k0; kt < k1; ++kt) {
-      // this wave's loads of stage kt have landed (later stages may still fly)
-      if (kt + PD - 1 < nk)
-        __builtin_amdgcn_s_waitcnt(WAIT_STEADY);
-      else
-        __builtin_amdgcn_s_waitcnt(0);
-      // ... and everyone's; the buffer of stage kt-1 is free.  A bare
-      // s_barrier: __syncthreads() would add a workgroup release fence, which
-      // waits for every outstanding LDS-DMA load and so drains the pipeline.
-      // The empty asm statements keep the compiler from moving LDS accesses
-      // across the barrier; the waits above provide the hardware ordering.
-      asm volatile("" ::: "memory");
-      __builtin_amdgcn_s_barrier();
-      asm volatile("" ::: "memory");
-      if (kt + PD < nk) issue(kt + PD, (kt + PD) % NBUF);
-      const T *st = smem + (kt % NBUF) * STAGE;
-      v4u af[4][NX], bf[NBJ][NX];
-#pragma unroll
-      for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-        for (int x = 0; x < NX; ++x) af[bi][x] = frag(st, rh * 64 + bi * 16 + l16, x);
-#pragma unroll
-      for (int bj = 0; bj < NBJ; ++bj)
-#pragma unroll
-        for (int x = 0; x < NX; ++x) bf[bj][x] = frag(st, AR + wc * WCOLS + bj * 16 + l16, x);
-#pragma unroll
-      for (int pr = 0; pr < NPR; ++pr)
-#pragma unroll
-        for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-          for (int bj = 0; bj < NBJ; ++bj) {
-            const int xa = NP == 1 ? QA[pr] : PA[pr], xb = NP == 1 ? QA[pr] : PB[pr];
-            acc[bi][bj] = mfma16<KIND>(af[bi][xa], bf[bj][xb], acc[bi][bj]);
-          }
-    }
+  v4u af[4][NX], bf[NBJ][NX];
+  auto read_frags = [&](int kt) {
+    const T *st = smem + (kt % NBUF) * STAGE;
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < NBJ; ++bj) {
-        tot[bi][bj] += acc[bi][bj];
-        acc[bi][bj] = v4f{};
+      for (int x = 0; x < NX; ++x) af[bi][x] = frag(st, rh * 64 + bi * 16 + l16, x);
+#pragma unroll
+    for (int bj = 0; bj < NBJ; ++bj)
+#pragma unroll
+      for (int x = 0; x < NX; ++x) bf[bj][x] = frag(st, AR + wc * WCOLS + bj * 16 + l16, x);
+  };
+  // the products of stage kt; the chunk accumulator goes into the running
+  // total after the last stage of each chunk of `fold` stages
+  auto compute = [&](int kt) {
+#pragma unroll
+    for (int pr = 0; pr < NPR; ++pr)
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < NBJ; ++bj) {
+          const int xa = NP == 1 ? QA[pr] : PA[pr], xb = NP == 1 ? QA[pr] : PB[pr];
+          acc[bi][bj] = mfma16<KIND>(af[bi][xa], bf[bj][xb], acc[bi][bj]);
+        }
+    if ((kt + 1) % fold == 0 || kt == nk - 1) {
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < NBJ; ++bj) {
+          tot[bi][bj] += acc[bi][bj];
+          acc[bi][bj] = v4f{};
+        }
+    }
+  };
+  // Bare s_barrier: __syncthreads() would add a workgroup release fence,
+  // which waits for every outstanding LDS-DMA load and so drains the
+  // pipeline.  The empty asm statements keep the compiler from moving LDS
+  // accesses across it, the scheduling barriers keep the matrix products on
+  // their side of it; the waits before it provide the hardware ordering.
+  auto barrier = [] {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" ::: "memory");
+  };
+  // this wave's loads of stage kt have landed (later stages may still fly)
+  // and its fragment reads are complete
+  auto wait_stage = [&](int kt) {
+    if (kt + PD - 1 < nk)
+      __builtin_amdgcn_s_waitcnt(WAIT_STEADY & ~(0xF << 8));
+    else
+      __builtin_amdgcn_s_waitcnt(0);
+  };
+  // Waves of a tile below the diagonal run the same instruction stream (their
+  // results are discarded).
+#pragma unroll
+  for (int s0 = 0; s0 < PD; ++s0)
+    if (s0 < nk) issue(s0, s0);
+  if constexpr (PING) {
+    // Two wave groups, waves 0-3 (A) and 4-7 (B), one of each per SIMD, half
+    // a stage apart: in the first half of stage kt A reads its fragments of
+    // stage kt while B runs its products of stage kt-1; in the second half A
+    // runs the products of stage kt while B reads its fragments of it.  Each
+    // SIMD's matrix core is fed by one group while the other waits on LDS.
+    // Each wave's products and their order are those of the plain loop.
+    // A wave whose load cannot issue stalls its whole instruction stream, so
+    // each group issues its share of the loads of stage kt+PD (into the
+    // buffer freed at the first barrier) in its fragment-read half only.
+    const bool grp_b = wave >= NW16 / 2;
+    for (int kt = 0; kt <= nk; ++kt) {
+      wait_stage(kt);
+      barrier();   // stage kt has landed; the buffer of stage kt-1 is free
+      if (!grp_b) {
+        if (kt + PD < nk) issue(kt + PD, (kt + PD) % NBUF);
+        if (kt < nk) read_frags(kt);
+      } else if (kt > 0) {
+        compute(kt - 1);
       }
+      barrier();
+      if (kt < nk) {
+        if (!grp_b) {
+          compute(kt);
+        } else {
+          if (kt + PD < nk) issue(kt + PD, (kt + PD) % NBUF);
+          read_frags(kt);
+        }
+      }
+    }
+  } else {
+    for (int kt = 0; kt < nk; ++kt) {
+      wait_stage(kt);
+      barrier();   // ... and everyone's; the buffer of stage kt-1 is free
+      if (kt + PD < nk) issue(kt + PD, (kt + PD) % NBUF);
+      read_frags(kt);
+      compute(kt);
+    }
   }
   __syncthreads();   // all waves done with the stage buffers (reused below)
 
