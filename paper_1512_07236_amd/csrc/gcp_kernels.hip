@@ -573,7 +573,14 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
   if (tvalid && !(dtile && br > bc)) {   // blocks below the diagonal are mirrors
     const bool dblk = dtile && br == bc;
     const int64_t j0 = (int64_t)tjj * TILE + bc * 8;
-    v4u ob[NP][8];   // encoded results, row r, 8 halves
+    // Encoded results, row r of the block, 8 halves per plane, kept for the
+    // mirrored store.  One- and two-plane encodings park them in this
+    // thread's own 8 x 8 block of V (32 bytes per row, already consumed when
+    // row r is encoded), which keeps them out of the registers; the
+    // three-plane ones hold them in registers.
+    constexpr bool PARK = NP <= 2;
+    v4u ob[PARK ? 1 : NP][8];
+    uint32_t *park = (uint32_t *)(V + (th * TILE + br * 8) * EPLD + bc * 8);   // row r at park + r * EPLD
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const int64_t i = i0 + r;
@@ -646,7 +653,10 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
         v4u w;
 #pragma unroll
         for (int q = 0; q < 4; ++q) w[q] = (uint32_t)o[p][2 * q] | ((uint32_t)o[p][2 * q + 1] << 16);
-        ob[p][r] = w;
+        if constexpr (PARK)
+          *(v4u *)(park + r * EPLD + 4 * p) = w;
+        else
+          ob[p][r] = w;
         if (!dblk) {
           *(v4u *)(Og + eoff<P>(i, j0, p, Mp)) = w;
         } else {
@@ -658,15 +668,23 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
     }
     // mirrored (transposed) block: row j0+e gets column e of the block
 #pragma unroll
-    for (int p = 0; p < NP; ++p)
+    for (int p = 0; p < NP; ++p) {
+      v4u obp[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        if constexpr (PARK)
+          obp[r] = *(const v4u *)(park + r * EPLD + 4 * p);
+        else
+          obp[r] = ob[p][r];
+      }
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         if (!dblk) {
           v4u w;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const uint32_t lo = (ob[p][2 * q][e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-            const uint32_t hi = (ob[p][2 * q + 1][e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+            const uint32_t lo = (obp[2 * q][e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+            const uint32_t hi = (obp[2 * q + 1][e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
             w[q] = lo | (hi << 16);
           }
           *(v4u *)(Og + eoff<P>(j0 + e, i0, p, Mp)) = w;
@@ -675,9 +693,10 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
           for (int r = 0; r < 8; ++r)
             if (r < e)
               Og[eoff<P>(j0 + e, i0 + r, p, Mp)] =
-                  (uint16_t)((ob[p][r][e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+                  (uint16_t)((obp[r][e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
         }
       }
+    }
   }
   // row sums: the 16 threads of a block row (lanes differing in bits 0..3)
 #pragma unroll
