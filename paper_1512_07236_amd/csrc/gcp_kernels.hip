@@ -574,12 +574,11 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
     const bool dblk = dtile && br == bc;
     const int64_t j0 = (int64_t)tjj * TILE + bc * 8;
     // Encoded results, row r of the block, 8 halves per plane, kept for the
-    // mirrored store.  One- and two-plane encodings park them in this
-    // thread's own 8 x 8 block of V (32 bytes per row, already consumed when
-    // row r is encoded), which keeps them out of the registers; the
-    // three-plane ones hold them in registers.
-    constexpr bool PARK = NP <= 2;
-    v4u ob[PARK ? 1 : NP][8];
+    // mirrored store.  Planes p < NPARK are parked in this thread's own 8 x 8
+    // block of V (32 bytes per row, already consumed when row r is encoded),
+    // which keeps them out of the registers; a third plane stays in them.
+    constexpr int NPARK = NP < 2 ? NP : 2;
+    v4u ob[NP > NPARK ? NP - NPARK : 1][8];
     uint32_t *park = (uint32_t *)(V + (th * TILE + br * 8) * EPLD + bc * 8);   // row r at park + r * EPLD
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
@@ -653,10 +652,10 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
         v4u w;
 #pragma unroll
         for (int q = 0; q < 4; ++q) w[q] = (uint32_t)o[p][2 * q] | ((uint32_t)o[p][2 * q + 1] << 16);
-        if constexpr (PARK)
+        if (p < NPARK)
           *(v4u *)(park + r * EPLD + 4 * p) = w;
         else
-          ob[p][r] = w;
+          ob[p - NPARK][r] = w;
         if (!dblk) {
           *(v4u *)(Og + eoff<P>(i, j0, p, Mp)) = w;
         } else {
@@ -672,10 +671,10 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
       v4u obp[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        if constexpr (PARK)
+        if (p < NPARK)
           obp[r] = *(const v4u *)(park + r * EPLD + 4 * p);
         else
-          obp[r] = ob[p][r];
+          obp[r] = ob[p - NPARK][r];
       }
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
