@@ -270,7 +270,7 @@ extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void
   c->Mp = (M + 255) / 256 * 256;   // whole pairs of 128-wide tiles
   c->nt = (int)(c->Mp / 128);
   c->ntiles = c->nt * (c->nt + 1) / 2;
-  c->nred = (int)((c->Mp + 255) / 256);
+  c->nred = (int)((c->Mp + 63) / 64);   // k_reduce blocks (64 rows each)
   c->opt = o;
   c->stream = (hipStream_t)stream;
   (void)hipGetDevice(&c->device);

@@ -944,21 +944,28 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a) {
 }
 
 // -------------------------------------------------------------- reductions
-// out[i] = sum_s part[s][i] (s ascending); per-block sums of out and of
-// extra; the last block to finish adds the block sums and the tile partials
-// in a fixed order and runs the scalar step for this point of the iteration.
+// out[i] = sum_s part[s][i]: a block covers 64 rows, wave q of it sums the
+// slots s = q (mod 4) in ascending order, and the four wave sums are added in
+// wave order.  Per-block sums of out and of extra; the last block to finish
+// adds the block sums and the tile partials in a fixed order and runs the
+// scalar step for this point of the iteration.
 __device__ __forceinline__ double ld_agent(const double *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
-  __shared__ double s1[256], s2[256], s3[256];
+  __shared__ double rq[4][64], s1[256], s2[256], s3[256];
   __shared__ int is_last;
-  const int tid = threadIdx.x;
-  const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+  const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  double w = 0.0;
+  if (i < a.Mp)
+    for (int s = q; s < a.nslots; s += 4) w += a.part[(int64_t)s * a.Mp + i];
+  rq[q][lane] = w;
+  __syncthreads();
   double v = 0.0, e = 0.0;
-  if (i < a.Mp) {
-    for (int s = 0; s < a.nslots; ++s) v += a.part[(int64_t)s * a.Mp + i];
+  if (q == 0 && i < a.Mp) {
+    v = ((rq[0][lane] + rq[1][lane]) + rq[2][lane]) + rq[3][lane];
     a.out[i] = v;
     if (a.extra) e = a.extra[i];
   }
@@ -1205,7 +1212,7 @@ hipError_t launch_hdev(const double *H, int64_t ldh, int64_t M, int64_t Mp, doub
 }
 
 hipError_t launch_reduce(const RedArgs &a, hipStream_t st) {
-  k_reduce<<<(unsigned)((a.Mp + 255) / 256), 256, 0, st>>>(a);
+  k_reduce<<<(unsigned)((a.Mp + 63) / 64), 256, 0, st>>>(a);
   return hipGetLastError();
 }
 
