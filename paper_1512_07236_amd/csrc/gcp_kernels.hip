@@ -211,9 +211,10 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
 // ------------------------------------------------ 16-bit product kernel
 // Pairs of horizontally adjacent 128 x 128 tiles, (ti, 2c) and (ti, 2c+1),
 // share one row panel of the left operand: a 128 x 256 output per block of
-// 4 waves, each wave 64 rows x 128 columns of one tile (4 x 8 MFMA blocks).
-// LDS is double-buffered (one barrier per K stage of 32).  All split
-// products of a K step go into one FP32 chunk accumulator, which is added
+// 8 waves (2 per SIMD), each wave 64 rows x 64 columns of one tile (4 x 4
+// MFMA blocks).  The panels stream through a 3-stage LDS ring, one K stage
+// of 32 per step.  All split products of a K step go into one FP32 chunk
+// accumulator, which is added
 // into a running FP32 total every `fold` K steps.  With r products per step
 // and n = K/32 steps the rounding error then grows like sqrt(r*fold + n/fold)
 // instead of sqrt(r*n): fold = sqrt(n/r) (the default) minimises it.  This
