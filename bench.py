@@ -137,9 +137,11 @@ def summarize_pmc(precision: str, scale: int, fetch_dir: str, write_dir: str) ->
     for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = [r for r in _counter_rows(d) if r["Counter_Name"] == name]
         kern = [float(r["Counter_Value"]) for r in rows if f"{kname}<{int(prec)}>" in r["Kernel_Name"]]
+        # the calibration copy: FETCH_SIZE reads about half of its true bytes
+        # (WRITE_SIZE all of them), so accept copy kernels above a quarter
         copy = [float(r["Counter_Value"]) for r in rows
                 if ("copy" in r["Kernel_Name"].lower() or "elementwise" in r["Kernel_Name"].lower())
-                and float(r["Counter_Value"]) * 1024 > 0.5 * COPY_BYTES]
+                and float(r["Counter_Value"]) * 1024 > 0.25 * COPY_BYTES]
         if not kern or not copy:
             print(f"no {name} rows for the kernel or the copy in {d}", file=sys.stderr)
             return 1
