@@ -41,13 +41,18 @@ extern "C" {
 typedef struct gcp_ctx gcp_ctx;
 
 typedef enum {
+    GCP_STOPPED_AT_FLOOR = 1,   /* not an error: |Tr(D Dbar)| stopped decreasing, or turned
+                                   negative, while already within the rounding floor of the
+                                   encoding (see floor_ddbar): the returned iterate is as
+                                   idempotent as the arithmetic allows, above tol_ddbar */
     GCP_OK = 0,
     GCP_ERR_INVALID_ARG = -1,   /* bad size, pointer, dtype, tolerance or bounds */
     GCP_ERR_HIP = -2,           /* a HIP runtime call failed (text in gcp_last_error) */
     GCP_ERR_NO_MEMORY = -3,     /* device or pinned-host allocation failed */
     GCP_ERR_NOT_CONVERGED = -4, /* max_iter updates applied without meeting a tolerance */
-    GCP_ERR_BREAKDOWN = -5,     /* c_n outside [0,1], Tr(D Dbar) < 0, or a non-finite
-                                   value before convergence (the paper's runaway case) */
+    GCP_ERR_BREAKDOWN = -5,     /* c_n outside [0,1], Tr(D Dbar) <= 0 above the rounding
+                                   floor, or a non-finite value before convergence (the
+                                   paper's runaway case) */
     GCP_ERR_STATE = -6,         /* call out of order (purify before init, ...) */
     GCP_ERR_UNSUPPORTED = -7    /* option combination not available */
 } gcp_status;
@@ -131,6 +136,20 @@ typedef struct {
                               (bitwise the same iterates), storing k iterates at a time:
                               memory p/k + k matrices instead of p, for two extra
                               products per update in the backward. */
+    int32_t sync_every;    /* gcp_purify enqueues this many updates between host checks of
+                              the termination decision (default 4; 1 = check after every
+                              D^2).  Each update's decision is taken on the device before c_n
+                              is formed, and launches enqueued past the stop do nothing, so
+                              the iterates and the history do not depend on it.  A precision
+                              schedule checks after every update until it has switched. */
+    int32_t pad2;
+    double floor_ddbar;    /* rounding floor of |Tr(D Dbar)|: NaN (default) = derived by the
+                              library from the encoding's unit roundoff and its accumulation
+                              scheme, 20 rho N / M with rho = u_enc + 2 u_acc sqrt(kappa) (kappa:
+                              rounding steps of a product element); 0 = none (every negative
+                              Tr(D Dbar) or c outside [0,1] is a breakdown).  Within the floor a
+                              stalled or negative Tr(D Dbar) stops the solve with
+                              GCP_STOPPED_AT_FLOOR instead of GCP_ERR_BREAKDOWN. */
 } gcp_options;
 
 enum { GCP_METHOD_HPCP = 0, GCP_METHOD_PMCP = 1 };
@@ -145,8 +164,8 @@ typedef struct {
     double idem;         /* ||D^2 - D||_F of the returned matrix (from the last D^2) */
     double ms_total;     /* wall time of gcp_purify on the host clock (ms) */
     double gemm_ms;      /* summed device time of the matrix-product launches (profile=1) */
-    int32_t gemm_launches; /* number of matrix-product launches */
-    int32_t pad;
+    int32_t gemm_launches; /* number of matrix-product launches that did work */
+    int32_t host_syncs;  /* host synchronisations of the iteration loop (gcp_purify) */
     double gemm_flops;   /* algorithmic flops of those launches (M^3 per product,
                             upper-triangle output; split products not counted) */
     double mfma_flops;   /* flops issued to the matrix cores (whole 128x128 tiles of the
@@ -178,8 +197,10 @@ int gcp_init(gcp_ctx *ctx, const double *H, int64_t ldh, int64_t N, double emin,
 /* Runs the recursion of eq. (hpcp3) from the current D_0 and writes the
  * converged density matrix to D (device, M x M, leading dimension ldd,
  * dtype gcp_dtype).  D is valid once the context's stream is synchronised.
- * Returns OK on convergence, NOT_CONVERGED or BREAKDOWN otherwise (D then
- * holds the last iterate and *out is filled in every case; out may be NULL).
+ * Returns OK on convergence, STOPPED_AT_FLOOR (a positive status, not an
+ * error) when the rounding floor of the encoding was reached above tol_ddbar,
+ * NOT_CONVERGED or BREAKDOWN otherwise (D then holds the last iterate and
+ * *out is filled in every case; out may be NULL).
  * Calling it again re-runs the solve from the D_0 of the last gcp_init. */
 int gcp_purify(gcp_ctx *ctx, void *D, int32_t dtype, int64_t ldd, gcp_result *out);
 

@@ -82,6 +82,8 @@ def lib():
         L.oracle_jacobi_eigh.argtypes = [i64, P, P, P, dbl, cint]
         L.oracle_jacobi_eigh.restype = cint
         L.oracle_projector.argtypes = [i64, i64, P, P]
+        L.oracle_update_at.argtypes = [i64, P, dbl, cint, P, P]
+        L.oracle_update_at.restype = cint
         _lib = L
     return _lib
 
@@ -214,6 +216,32 @@ def purify_from(D0: np.ndarray, N: int, tol_ddbar: float = 1e-6, tol_idem: float
                                     _p(hist), ctypes.byref(iters))
     n = iters.value
     return Result(D, st, n, hist[: n + 1].copy())
+
+
+def update_at(D: np.ndarray, c: float = float("nan"), method: str = "hpcp"):
+    """One update of the recursion from the symmetric D at the given c (plain
+    C, FP64): eq. (hpcp3) for method "hpcp", eqs. (pm1a)/(pm1b) for "pmcp";
+    c = NaN uses the coefficient eq. (hpcp3) forms from D itself.  Returns
+    (D', (Tr D, Tr D^2, Tr D^3, c_own)) with c_own = Tr(D^2 Dbar)/Tr(D Dbar)
+    from the same products."""
+    D = _f64(D)
+    M = D.shape[0]
+    out = np.empty((M, M))
+    tr = np.empty(4)
+    if lib().oracle_update_at(M, _p(D), float(c), METHODS[method], _p(out), _p(tr)) != OK:
+        raise MemoryError("update_at: allocation failed")
+    return out, tuple(float(x) for x in tr)
+
+
+def power_traces(D: np.ndarray):
+    """Tr D, Tr D^2, Tr D^3 and c = (Tr D^2 - Tr D^3)/(Tr D - Tr D^2) of a
+    symmetric D by their definitions (FP64; Tr D^2 = sum of D o D and
+    Tr D^3 = sum of (D D) o D, one library matmul), for sizes where the plain
+    C product would be slow."""
+    D = _f64(D)
+    X2 = D @ D
+    t1, t2, t3 = float(np.trace(D)), float(np.sum(D * D)), float(np.sum(X2 * D))
+    return t1, t2, t3, (t2 - t3) / (t1 - t2)
 
 
 def jacobi_eigh(A: np.ndarray, tol: float = 1e-15, max_sweeps: int = 60):

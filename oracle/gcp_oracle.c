@@ -358,6 +358,51 @@ int oracle_purify_from_m(int64_t M, int64_t N, double *D, int method, double tol
     return status;
 }
 
+/*
+ * One update of the recursion from a symmetric D at a GIVEN coefficient c:
+ * method 0 applies eq. (hpcp3), D' = D + 2 (D^2 Dbar - c D Dbar); method 1
+ * eq. (pm1a) for c <= 1/2 and eq. (pm1b) for c > 1/2.  The result is
+ * symmetrised, out = (T + T^T)/2.  tr[0..3] receives Tr D, Tr D^2, Tr D^3 of
+ * the products formed here and the coefficient Tr(D^2 Dbar)/Tr(D Dbar) that
+ * eq. (hpcp3) itself would use; c = NaN applies that coefficient.  This is
+ * the single step of oracle_purify_from_m with c supplied from outside, so a
+ * recursion computed elsewhere can be checked one update at a time from its
+ * own iterate and its own c.  Returns ORACLE_OK or ORACLE_INVALID (no memory).
+ */
+int oracle_update_at(int64_t M, const double *D, double c, int method, double *out, double *tr)
+{
+    const int64_t MM = M * M;
+    double *X2 = (double *)malloc(sizeof(double) * MM);
+    double *X3 = (double *)malloc(sizeof(double) * MM);
+    if (!X2 || !X3) {
+        free(X2); free(X3);
+        return ORACLE_INVALID;
+    }
+    oracle_matmul(M, D, D, X2);
+    oracle_matmul(M, X2, D, X3);
+    const double t1 = trace(M, D), t2 = trace(M, X2), t3 = trace(M, X3);
+    const double c_own = (t2 - t3) / (t1 - t2);
+    if (tr) { tr[0] = t1; tr[1] = t2; tr[2] = t3; tr[3] = c_own; }
+    if (isnan(c)) c = c_own;
+    for (int64_t e = 0; e < MM; ++e) {
+        double t;
+        if (method == 0) {
+            const double d2dbar = X2[e] - X3[e];   /* (D^2 Dbar)_e */
+            const double ddbar = D[e] - X2[e];     /* (D Dbar)_e */
+            t = D[e] + 2.0 * (d2dbar - c * ddbar);
+        } else if (c <= 0.5) {
+            t = ((1.0 - 2.0 * c) * D[e] + (1.0 + c) * X2[e] - X3[e]) / (1.0 - c);
+        } else {
+            t = ((1.0 + c) * X2[e] - X3[e]) / c;
+        }
+        X3[e] = t;   /* X3[e] is not read again */
+    }
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = 0; j < M; ++j) out[i * M + j] = 0.5 * (X3[i * M + j] + X3[j * M + i]);
+    free(X2); free(X3);
+    return ORACLE_OK;
+}
+
 int oracle_purify_from(int64_t M, int64_t N, double *D, double tol_ddbar,
                        double tol_idem, int max_iter, double *hist, int *iters)
 {

@@ -55,7 +55,10 @@ MFMA_DTYPE = {Precision.FP64: "fp64", Precision.FP32: "fp32", Precision.BF16: "b
 
 OK, ERR_INVALID_ARG, ERR_HIP, ERR_NO_MEMORY, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_STATE, \
     ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
-STATUS_NAMES = {OK: "OK", ERR_INVALID_ARG: "INVALID_ARG", ERR_HIP: "HIP", ERR_NO_MEMORY: "NO_MEMORY",
+# not an error: the rounding floor of the encoding was reached above tol_ddbar
+STOPPED_AT_FLOOR = 1
+SUCCESS = (OK, STOPPED_AT_FLOOR)
+STATUS_NAMES = {OK: "OK", STOPPED_AT_FLOOR: "STOPPED_AT_FLOOR", ERR_INVALID_ARG: "INVALID_ARG", ERR_HIP: "HIP", ERR_NO_MEMORY: "NO_MEMORY",
                 ERR_NOT_CONVERGED: "NOT_CONVERGED", ERR_BREAKDOWN: "BREAKDOWN",
                 ERR_STATE: "STATE", ERR_UNSUPPORTED: "UNSUPPORTED"}
 DTYPE_F64, DTYPE_F32 = 0, 1
@@ -72,7 +75,8 @@ class Options(ctypes.Structure):
                 ("switch_ddbar", ctypes.c_double), ("method", ctypes.c_int32),
                 ("init_mode", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("delta", ctypes.c_double), ("hole", ctypes.c_int32),
-                ("checkpoint_every", ctypes.c_int32)]
+                ("checkpoint_every", ctypes.c_int32), ("sync_every", ctypes.c_int32),
+                ("pad2", ctypes.c_int32), ("floor_ddbar", ctypes.c_double)]
 
 
 METHODS = {"hpcp": 0, "pmcp": 1}           # the recursion
@@ -84,7 +88,7 @@ class CResult(ctypes.Structure):
                 ("t1", ctypes.c_double), ("t2", ctypes.c_double), ("c_last", ctypes.c_double),
                 ("idem", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("gemm_ms", ctypes.c_double), ("gemm_launches", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("gemm_flops", ctypes.c_double),
+                ("host_syncs", ctypes.c_int32), ("gemm_flops", ctypes.c_double),
                 ("mfma_flops", ctypes.c_double)]
 
 
@@ -156,10 +160,12 @@ class Result:
     gemm_flops: float
     mfma_flops: float
     history: np.ndarray
+    host_syncs: int = 0
 
     @property
     def ok(self) -> bool:
-        return self.status == OK
+        """Converged to the tolerance, or stopped at the encoding's rounding floor."""
+        return self.status in SUCCESS
 
     def col(self, name: str) -> np.ndarray:
         return self.history[:, HIST_FIELDS.index(name)]
@@ -180,7 +186,8 @@ class Context:
                  keep_iterates: bool = False, bwd_precision="fp64", late_precision=None,
                  switch_ddbar: float = 0.0, method: str = "hpcp", init: str = "pmcp",
                  alpha: float = 0.5, delta: float = 2.0 / 3.0, hole: bool = False,
-                 checkpoint_every: int = 0, stream=None):
+                 checkpoint_every: int = 0, sync_every: int = 4,
+                 floor_ddbar: float = math.nan, stream=None):
         L = load_library()
         self._L = L
         self.M = int(M)
@@ -202,11 +209,16 @@ class Context:
         o.delta = float(delta)
         o.hole = 1 if hole else 0
         o.checkpoint_every = int(checkpoint_every)
+        o.sync_every = int(sync_every)
+        o.floor_ddbar = float(floor_ddbar)
         self.options = o
-        self._stream = stream
+        import torch
+        # the library works on this stream; calls made while another stream is
+        # current first make it wait for that stream (inputs written there)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
         st = L.gcp_create(ctypes.byref(h), self.M, ctypes.byref(o),
-                          ctypes.c_void_p(_stream_handle(stream)))
+                          ctypes.c_void_p(_stream_handle(self._stream)))
         if st != OK:
             raise GCPError(st, L.gcp_last_error(None).decode())
         self._h = h
@@ -217,13 +229,22 @@ class Context:
             raise GCPError(st, self._L.gcp_last_error(self._h).decode())
         return st
 
+    def _handle(self):
+        if not getattr(self, "_h", None):
+            raise GCPError(ERR_STATE, "the context is closed")
+        import torch
+        cur = torch.cuda.current_stream()
+        if cur != self._stream:
+            self._stream.wait_stream(cur)
+        return self._h
+
     def init(self, H, N: int, emin: float = math.nan, emax: float = math.nan) -> None:
         import torch
         if not (isinstance(H, torch.Tensor) and H.is_cuda and H.dtype == torch.float64):
             raise TypeError("H must be a CUDA float64 tensor")
         if H.dim() != 2 or H.shape[0] != self.M or H.shape[1] != self.M or H.stride(1) != 1:
             raise ValueError(f"H must be {self.M} x {self.M} with unit column stride")
-        self._check(self._L.gcp_init(self._h, ctypes.c_void_p(H.data_ptr()), H.stride(0), int(N),
+        self._check(self._L.gcp_init(self._handle(), ctypes.c_void_p(H.data_ptr()), H.stride(0), int(N),
                                      float(emin), float(emax)))
         self.N = int(N)
 
@@ -238,12 +259,13 @@ class Context:
             raise ValueError("out must be an M x M float64/float32 CUDA tensor with unit column stride")
         dt = DTYPE_F64 if out.dtype == torch.float64 else DTYPE_F32
         r = CResult()
-        st = self._L.gcp_purify(self._h, ctypes.c_void_p(out.data_ptr()), dt, out.stride(0),
+        st = self._L.gcp_purify(self._handle(), ctypes.c_void_p(out.data_ptr()), dt, out.stride(0),
                                 ctypes.byref(r))
-        allowed = (OK,) if raise_on_failure else (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN)
+        allowed = SUCCESS if raise_on_failure else SUCCESS + (ERR_NOT_CONVERGED, ERR_BREAKDOWN)
         self._check(st, allowed)
         return out, Result(r.status, r.iters, r.t1, r.t2, r.c_last, r.idem, r.ms_total, r.gemm_ms,
-                           r.gemm_launches, r.gemm_flops, r.mfma_flops, self.history())
+                           r.gemm_launches, r.gemm_flops, r.mfma_flops, self.history(),
+                           r.host_syncs)
 
     def backward(self, dL_dD, out=None):
         """dL/dH for the loss gradient dL_dD of the last purify's result
@@ -260,7 +282,7 @@ class Context:
             raise ValueError("out must match dL_dD's dtype and shape with unit column stride")
         dt = DTYPE_F64 if out.dtype == torch.float64 else DTYPE_F32
         r = CResult()
-        self._check(self._L.gcp_backward(self._h, ctypes.c_void_p(dL_dD.data_ptr()),
+        self._check(self._L.gcp_backward(self._handle(), ctypes.c_void_p(dL_dD.data_ptr()),
                                          dL_dD.stride(0), ctypes.c_void_p(out.data_ptr()),
                                          out.stride(0), dt, ctypes.byref(r)))
         return out, Result(r.status, r.iters, r.t1, r.t2, r.c_last, r.idem, r.ms_total, r.gemm_ms,
@@ -276,7 +298,7 @@ class Context:
                 raise ValueError(f"{name} must be an M x M CUDA tensor of {dts} with unit column stride")
         dt = DTYPE_F64 if D.dtype == torch.float64 else DTYPE_F32
         r = CVerify()
-        self._check(self._L.gcp_verify(self._h, ctypes.c_void_p(D.data_ptr()), dt, D.stride(0),
+        self._check(self._L.gcp_verify(self._handle(), ctypes.c_void_p(D.data_ptr()), dt, D.stride(0),
                                        ctypes.c_void_p(H.data_ptr()), H.stride(0), ctypes.byref(r)))
         return {k: getattr(r, k) for k, _ in CVerify._fields_}
 
@@ -329,17 +351,26 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, H, N, emin, emax, options):
+            options = dict(options)
+            retain = bool(options.pop("retain_iterates", False))
             c = Context(H.shape[0], keep_iterates=True, **options)
             c.init(H.detach().contiguous(), N, emin, emax)
             D, res = c.purify(dtype=H.dtype, raise_on_failure=True)
             ctx.gcp = c
+            ctx.retain = retain
             ctx.result = res
             return D
 
         @staticmethod
         def backward(ctx, gD):
+            if ctx.gcp is None:
+                raise RuntimeError(
+                    "purify_autograd: backward ran already and released the stored iterates; "
+                    "pass retain_iterates=True to differentiate the same solve more than once")
             dH, _ = ctx.gcp.backward(gD.contiguous())
-            ctx.gcp.close()
+            if not ctx.retain:
+                ctx.gcp.close()   # the p stored iterates are released now
+                ctx.gcp = None
             return dH, None, None, None, None
 
     return _Purify
@@ -351,7 +382,9 @@ _PURIFY_FN = None
 def purify_autograd(H, N: int, emin: float = math.nan, emax: float = math.nan, **options):
     """Differentiable D(H): a torch.autograd.Function whose backward is the
     library's adjoint (gcp_backward).  The context, with its stored iterates,
-    lives until the backward has run.  options are those of Context (FP64 H)."""
+    lives until the backward has run (or, with retain_iterates=True, until the
+    graph is freed, so that backward may run more than once).  Other options
+    are those of Context (FP64 H)."""
     global _PURIFY_FN
     if _PURIFY_FN is None:
         _PURIFY_FN = _autograd_function()

@@ -20,7 +20,19 @@ using namespace gcp;
 
 namespace {
 
-thread_local std::string g_create_error;
+// Text of the last error, in a fixed buffer: no path of the library that
+// runs a solve allocates host memory for its messages.
+struct ErrText {
+  char buf[320] = {0};
+  ErrText &operator=(const char *m) {
+    std::snprintf(buf, sizeof(buf), "%s", m);
+    return *this;
+  }
+  void set(const char *a, const char *b) { std::snprintf(buf, sizeof(buf), "%s: %s", a, b); }
+  const char *c_str() const { return buf; }
+};
+
+thread_local ErrText g_create_error;
 
 int plane_count(int prec) {
   switch (prec) {
@@ -72,6 +84,7 @@ struct gcp_ctx {
     int fold = 1;     // fold period of the 16-bit kernel (K stages)
     int nfull = 0;    // 16-bit kernel: pairs computed whole ...
     int nsplit = 1;   // ... and K splits of each remaining pair
+    double floor_ddbar = 0.0;   // rounding floor of |Tr(D Dbar)| (set by gcp_init)
   } pc[2];
   int nprec = 1;
   void *Xc = nullptr;       // conversion target of a precision switch
@@ -112,14 +125,14 @@ struct gcp_ctx {
   double *vD = nullptr, *vH = nullptr, *vHD = nullptr, *vaux = nullptr;
   // profiling
   std::vector<hipEvent_t> events;
-  std::string err;
+  ErrText err;
 };
 
 #define HIPCHK(ctx, expr)                                                          \
   do {                                                                             \
     hipError_t e_ = (expr);                                                        \
     if (e_ != hipSuccess) {                                                        \
-      (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(e_);             \
+      (ctx)->err.set(#expr, hipGetErrorString(e_));                                \
       return GCP_ERR_HIP;                                                          \
     }                                                                              \
   } while (0)
@@ -219,53 +232,52 @@ extern "C" int gcp_options_default(gcp_options *opt) {
   opt->delta = 2.0 / 3.0;
   opt->hole = 0;
   opt->checkpoint_every = 0;
+  opt->sync_every = 4;
+  opt->floor_ddbar = NAN;
   return GCP_OK;
 }
 
-extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void *stream) {
-  if (!out) {
-    g_create_error = "gcp_create: ctx pointer is NULL";
-    return GCP_ERR_INVALID_ARG;
-  }
-  *out = nullptr;
-  gcp_options o;
-  if (opt) o = *opt; else gcp_options_default(&o);
+// Checks the options and the size; the message goes to err.
+static int check_options(const gcp_options &o, int64_t M, ErrText &err) {
   if (M <= 0 || M > (int64_t)1 << 20) {
-    g_create_error = "gcp_create: M must be in [1, 2^20]";
+    err = "gcp_create: M must be in [1, 2^20]";
     return GCP_ERR_INVALID_ARG;
   }
   if (o.precision < GCP_FP64 || o.precision > GCP_BF16X6) {
-    g_create_error = "gcp_create: unknown precision";
+    err = "gcp_create: unknown precision";
     return GCP_ERR_INVALID_ARG;
   }
   if (o.max_iter < 0 || o.max_iter > 100000 || !(o.tol_ddbar >= 0.0) || !(o.tol_idem >= 0.0) ||
       o.fold_every < 0) {
-    g_create_error = "gcp_create: max_iter, tolerances and fold_every must be non-negative";
+    err = "gcp_create: max_iter, tolerances and fold_every must be non-negative";
     return GCP_ERR_INVALID_ARG;
   }
   if ((o.keep_iterates != 0 && o.keep_iterates != 1) ||
       (o.bwd_precision != GCP_FP64 && o.bwd_precision != GCP_FP32)) {
-    g_create_error = "gcp_create: keep_iterates must be 0 or 1 and bwd_precision FP64 or FP32";
+    err = "gcp_create: keep_iterates must be 0 or 1 and bwd_precision FP64 or FP32";
     return GCP_ERR_INVALID_ARG;
   }
   if (o.late_precision < -1 || o.late_precision > GCP_BF16X6 || !(o.switch_ddbar >= 0.0)) {
-    g_create_error = "gcp_create: late_precision must be -1 or a precision, switch_ddbar >= 0";
+    err = "gcp_create: late_precision must be -1 or a precision, switch_ddbar >= 0";
+    return GCP_ERR_INVALID_ARG;
+  }
+  if (o.sync_every < 1 || !(std::isnan(o.floor_ddbar) || o.floor_ddbar >= 0.0)) {
+    err = "gcp_create: sync_every must be >= 1 and floor_ddbar NaN or >= 0";
     return GCP_ERR_INVALID_ARG;
   }
   if (o.method < GCP_METHOD_HPCP || o.method > GCP_METHOD_PMCP || o.init_mode < GCP_INIT_PMCP ||
       o.init_mode > GCP_INIT_HP_SEARCH || !(o.alpha >= 0.0 && o.alpha <= 1.0) ||
       !(o.delta > 0.5 && o.delta < 1.0) || (o.hole != 0 && o.hole != 1) ||
       o.checkpoint_every < 0) {
-    g_create_error =
-        "gcp_create: method, init_mode, alpha in [0,1], delta in (1/2,1), hole or checkpoint_every "
-        "invalid";
+    err = "gcp_create: method, init_mode, alpha in [0,1], delta in (1/2,1), hole or "
+          "checkpoint_every invalid";
     return GCP_ERR_INVALID_ARG;
   }
-  gcp_ctx *c = new (std::nothrow) gcp_ctx();
-  if (!c) {
-    g_create_error = "gcp_create: out of host memory";
-    return GCP_ERR_NO_MEMORY;
-  }
+  return GCP_OK;
+}
+
+// Sizes and launch configuration of a context for M x M problems.
+static void setup_ctx(gcp_ctx *c, int64_t M, const gcp_options &o, void *stream) {
   c->M = M;
   c->Mp = (M + 255) / 256 * 256;   // whole pairs of 128-wide tiles
   c->nt = (int)(c->Mp / 128);
@@ -287,64 +299,96 @@ extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void
     PrecCfgInit(c, k);
     if (c->pc[k].ntpart > c->ntpart) c->ntpart = c->pc[k].ntpart;
   }
+}
 
+// Tile pairs of the K-split tail of the 16-bit kernel (for any encoding of
+// the context) and the largest split count.
+static void split_tail(const gcp_ctx *c, int &tail, int &smax) {
+  tail = 0;
+  smax = 1;
+  for (int k = 0; k < c->nprec; ++k)
+    if (c->pc[k].nsplit > 1) {
+      tail = pair_count(c->nt) - c->pc[k].nfull;
+      if (c->pc[k].nsplit > smax) smax = c->pc[k].nsplit;
+    }
+}
+
+// Every device buffer of the context with its size, in a fixed order.
+// one_shot: a solve that is neither re-run from its D_0 nor differentiated,
+// whose D_0 is built in place in the first D buffer.
+template <class F>
+static void for_each_buffer(gcp_ctx *c, bool one_shot, F &&f) {
   const size_t Mp = (size_t)c->Mp;
   const size_t vec = Mp * sizeof(double);
-  const int nslots_max = (int)(c->Mp / 64);  // the initial guess uses 64-wide column slots
+  const size_t nslots_max = Mp / 64;   // the initial guess uses 64-wide column slots
+  const size_t pb = plane_bytes(c);
+  f(&c->Dp[0], pb);
+  f(&c->Dp[1], pb);
+  f(&c->X2p, pb);
+  if (!one_shot) f(&c->D0p, pb);
+  for (int k = 0; k < 2; ++k) {
+    f((void **)&c->dg[k], vec);
+    f((void **)&c->rD[k], vec);
+    f((void **)&c->d2[k], vec);
+  }
+  f((void **)&c->s2, vec);
+  f((void **)&c->d3, vec);
+  if (!one_shot) {
+    f((void **)&c->dg0, vec);
+    f((void **)&c->rD0, vec);
+    f((void **)&c->d20, vec);
+  }
+  f((void **)&c->part, nslots_max * vec);
+  f((void **)&c->tpart, (size_t)c->ntpart * sizeof(double));
+  f((void **)&c->bpart, (size_t)2 * c->nred * sizeof(double));
+  f((void **)&c->hvec, 3 * vec);
+  f((void **)&c->counter, sizeof(unsigned));
+  f((void **)&c->sc, sizeof(Scalars));
+  f((void **)&c->hist, (size_t)(c->opt.max_iter + 1) * GCP_HIST_COLS * sizeof(double));
+  int tail, smax;
+  split_tail(c, tail, smax);
+  if (tail > 0) {
+    // one FP32 partial tile of 128 x 256 per split block
+    f((void **)&c->g16_ws, (size_t)tail * smax * 512 * 64 * sizeof(float));
+    f((void **)&c->g16_cnt, (size_t)tail * sizeof(unsigned));
+  }
+  if (c->nprec > 1) f(&c->Xc, pb);
+  if (!one_shot && c->opt.keep_iterates) {
+    const size_t bb = Mp * Mp * (size_t)elem_size(c->opt.bwd_precision);
+    f(&c->bG[0], bb);
+    f(&c->bG[1], bb);
+    f(&c->bX2, bb);
+    f(&c->bAT, bb);
+    f(&c->bCT, bb);
+    f((void **)&c->btpart, (size_t)c->nt * (c->nt + 1) / 2 * sizeof(double));
+    f((void **)&c->bvec, (2 * Mp + 8) * sizeof(double));
+  }
+}
+
+extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void *stream) {
+  if (!out) {
+    g_create_error = "gcp_create: ctx pointer is NULL";
+    return GCP_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  gcp_options o;
+  if (opt) o = *opt; else gcp_options_default(&o);
+  int st = check_options(o, M, g_create_error);
+  if (st != GCP_OK) return st;
+  gcp_ctx *c = new (std::nothrow) gcp_ctx();
+  if (!c) {
+    g_create_error = "gcp_create: out of host memory";
+    return GCP_ERR_NO_MEMORY;
+  }
+  setup_ctx(c, M, o, stream);
   bool ok = true;
-  auto alloc = [&](void **p, size_t bytes) {
+  for_each_buffer(c, false, [&](void **p, size_t bytes) {
     if (!ok) return;
     if (hipMalloc(p, bytes) != hipSuccess) {
       ok = false;
       *p = nullptr;
     }
-  };
-  const size_t pb = plane_bytes(c);
-  alloc(&c->Dp[0], pb);
-  alloc(&c->Dp[1], pb);
-  alloc(&c->X2p, pb);
-  alloc(&c->D0p, pb);
-  for (int k = 0; k < 2; ++k) {
-    alloc((void **)&c->dg[k], vec);
-    alloc((void **)&c->rD[k], vec);
-    alloc((void **)&c->d2[k], vec);
-  }
-  alloc((void **)&c->s2, vec);
-  alloc((void **)&c->d3, vec);
-  alloc((void **)&c->dg0, vec);
-  alloc((void **)&c->rD0, vec);
-  alloc((void **)&c->d20, vec);
-  alloc((void **)&c->part, (size_t)nslots_max * vec);
-  alloc((void **)&c->tpart, (size_t)c->ntpart * sizeof(double));
-  alloc((void **)&c->bpart, (size_t)2 * c->nred * sizeof(double));
-  alloc((void **)&c->hvec, 3 * vec);
-  alloc((void **)&c->counter, sizeof(unsigned));
-  alloc((void **)&c->sc, sizeof(Scalars));
-  alloc((void **)&c->hist, (size_t)(o.max_iter + 1) * GCP_HIST_COLS * sizeof(double));
-  {
-    // K-split tail of the 16-bit kernel: partial tiles for the largest split
-    int tail = 0, smax = 1;
-    for (int k = 0; k < c->nprec; ++k)
-      if (c->pc[k].nsplit > 1) {
-        tail = pair_count(c->nt) - c->pc[k].nfull;
-        if (c->pc[k].nsplit > smax) smax = c->pc[k].nsplit;
-      }
-    if (tail > 0) {
-      alloc((void **)&c->g16_ws, (size_t)tail * smax * 512 * 64 * sizeof(float));
-      alloc((void **)&c->g16_cnt, (size_t)tail * sizeof(unsigned));
-    }
-  }
-  if (c->nprec > 1) alloc(&c->Xc, pb);
-  if (o.keep_iterates) {
-    const size_t bb = Mp * Mp * (size_t)elem_size(o.bwd_precision);
-    alloc(&c->bG[0], bb);
-    alloc(&c->bG[1], bb);
-    alloc(&c->bX2, bb);
-    alloc(&c->bAT, bb);
-    alloc(&c->bCT, bb);
-    alloc((void **)&c->btpart, (size_t)c->nt * (c->nt + 1) / 2 * sizeof(double));
-    alloc((void **)&c->bvec, (2 * Mp + 8) * sizeof(double));
-  }
+  });
   if (ok && hipHostMalloc((void **)&c->sc_host, sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
     ok = false;
   if (!ok) {
@@ -353,9 +397,9 @@ extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void
     g_create_error = "gcp_create: device allocation failed";
     return GCP_ERR_NO_MEMORY;
   }
-  int ntail = 0;
-  for (int k = 0; k < c->nprec; ++k)
-    if (c->pc[k].nsplit > 1) ntail = pair_count(c->nt) - c->pc[k].nfull;
+  int ntail, smax;
+  split_tail(c, ntail, smax);
+  const size_t vec = (size_t)c->Mp * sizeof(double);
   if ((c->g16_cnt && hipMemsetAsync(c->g16_cnt, 0, (size_t)ntail * sizeof(unsigned),
                                      c->stream) != hipSuccess) ||
       hipMemsetAsync(c->counter, 0, sizeof(unsigned), c->stream) != hipSuccess ||
@@ -382,7 +426,8 @@ extern "C" const char *gcp_last_error(const gcp_ctx *c) {
 }
 
 static int reduce(gcp_ctx *c, const double *part, int nslots, int mode, double *out,
-                  const double *extra, const double *tpart, int ntp, int iter) {
+                  const double *extra, const double *tpart, int ntp, int iter,
+                  bool skip_if_stopped = false, double floor_ddbar = 0.0) {
   RedArgs a{};
   a.part = part;
   a.nslots = nslots;
@@ -399,6 +444,8 @@ static int reduce(gcp_ctx *c, const double *part, int nslots, int mode, double *
   a.tol_ddbar = c->opt.tol_ddbar;
   a.tol_idem = c->opt.tol_idem;
   a.N = (double)(c->opt.hole ? c->M - c->N : c->N);   // trace of the purified matrix
+  a.floor_ddbar = floor_ddbar;
+  a.skip_if_stopped = skip_if_stopped ? 1 : 0;
   a.sc = c->sc;
   a.hist = c->hist;
   HIPCHK(c, launch_reduce(a, c->stream));
@@ -408,6 +455,41 @@ static int reduce(gcp_ctx *c, const double *part, int nslots, int mode, double *
 static int build_guess(gcp_ctx *c, const double *H, int64_t ldh, double theta, double beta,
                        double mu);
 static int first_traces(gcp_ctx *c);
+
+// Rounding floor of |Tr(D Dbar)| for encoding pc[k] (unless the caller gave
+// one).  One update leaves an off-diagonal error of relative size
+// rho = u_enc + 2 u_acc sqrt(kappa) (encoding of the result, and the
+// accumulation of the product over kappa rounding steps, statistically)
+// on elements of typical size sqrt(N)/M.  The diagonal is exact, so near a
+// projector P the error E moves Tr(D Dbar) by Tr(E (I - 2P)) = -2 Tr(E P),
+// a sum with standard deviation 2 rho sqrt(N)/M ||P||_F = 2 rho N / M.  The
+// floor is ten times that.
+static double rounding_floor(const gcp_ctx *c, int k) {
+  if (!std::isnan(c->opt.floor_ddbar)) return c->opt.floor_ddbar;
+  const int prec = c->pc[k].prec;
+  double u_enc = 0.0;
+  switch (prec) {
+    case GCP_FP32: u_enc = std::ldexp(1.0, -24); break;
+    case GCP_BF16: u_enc = std::ldexp(1.0, -8); break;     // 8-bit significand
+    case GCP_FP16: u_enc = std::ldexp(1.0, -11); break;    // 11-bit significand
+    case GCP_BF16X3: u_enc = std::ldexp(1.0, -16); break;
+    case GCP_FP16X3: u_enc = std::ldexp(1.0, -22); break;
+    case GCP_BF16X6: u_enc = std::ldexp(1.0, -24); break;
+    default: break;
+  }
+  const double u_acc = std::ldexp(1.0, prec == GCP_FP64 ? -53 : -24);
+  double kappa = (double)c->Mp + 1.0;   // one accumulator over K
+  if (elem_size(prec) == 2) {
+    const int np = plane_count(prec);
+    const double stages = np <= 2 ? (double)c->Mp * np / 64.0 : (double)c->Mp / 32.0;
+    const double per_stage = np == 1 ? 2.0 : (double)products(prec);
+    const double f = (double)c->pc[k].fold;
+    kappa = 32.0 * per_stage * f + stages / f;
+  }
+  const double rho = u_enc + 2.0 * u_acc * std::sqrt(kappa);
+  const double n_eff = (double)(c->opt.hole ? c->M - c->N : c->N);
+  return 20.0 * rho * n_eff / (double)c->M;
+}
 
 // Fields of the product launch that do not change within a solve.
 static void setup_gemm(gcp_ctx *c, GemmArgs &g, int pi) {
@@ -426,6 +508,7 @@ static void setup_gemm(gcp_ctx *c, GemmArgs &g, int pi) {
   g.s2 = c->s2;
   g.d3 = c->d3;
   g.coef = &c->sc->c;
+  g.status = nullptr;   // set by gcp_purify's loop
 }
 
 extern "C" int gcp_init(gcp_ctx *c, const double *H, int64_t ldh, int64_t N, double emin,
@@ -523,6 +606,7 @@ extern "C" int gcp_init(gcp_ctx *c, const double *H, int64_t ldh, int64_t N, dou
   c->alpha = alpha;
   c->alpha_searched = searched;
   c->beta = beta;
+  for (int k = 0; k < c->nprec; ++k) c->pc[k].floor_ddbar = rounding_floor(c, k);
   (void)vec;
   c->inited = true;
   return GCP_OK;
@@ -607,7 +691,6 @@ static int store_iterate(gcp_ctx *c, int n, int k, int prec) {
 struct LaunchLog {
   bool prof = false;
   int n = 0;
-  double mfma_flops = 0.0;
 };
 
 // One product launch in encoding pc[pi].
@@ -620,11 +703,7 @@ static int run_product(gcp_ctx *c, GemmArgs &g, int pi, LaunchLog *log) {
   if (ev) HIPCHK(c, hipEventRecord(c->events[2 * log->n], c->stream));
   HIPCHK(c, launch_gemm(q.prec, g, c->stream));
   if (ev) HIPCHK(c, hipEventRecord(c->events[2 * log->n + 1], c->stream));
-  if (log) {
-    ++log->n;
-    log->mfma_flops +=
-        (double)c->ntiles * 2.0 * 128.0 * 128.0 * (double)c->Mp * (double)products(q.prec);
-  }
+  if (log) ++log->n;
   return GCP_OK;
 }
 
@@ -639,7 +718,8 @@ static int step_k1(gcp_ctx *c, GemmArgs &g, int pi, int k, int n, LaunchLog *log
   g.d2 = c->d2[k];
   int st = run_product(c, g, pi, log);
   if (st != GCP_OK) return st;
-  return reduce(c, c->part, c->nt, 1, c->d3, nullptr, c->tpart, c->pc[pi].ntpart, n);
+  return reduce(c, c->part, c->nt, 1, c->d3, nullptr, c->tpart, c->pc[pi].ntpart, n,
+                g.status != nullptr, c->pc[pi].floor_ddbar);
 }
 
 // K2 of update n: D_{n+1} into buffer 1 - k.
@@ -652,7 +732,8 @@ static int step_k2(gcp_ctx *c, GemmArgs &g, int pi, int k, int n, LaunchLog *log
   g.rD_new = c->rD[1 - k];
   int st = run_product(c, g, pi, log);
   if (st != GCP_OK) return st;
-  return reduce(c, c->part, c->nt, 2, c->d2[1 - k], c->dg[1 - k], c->tpart, c->pc[pi].ntpart, n);
+  return reduce(c, c->part, c->nt, 2, c->d2[1 - k], c->dg[1 - k], c->tpart, c->pc[pi].ntpart, n,
+                g.status != nullptr);
 }
 
 // Precision schedule: re-encode D_n (buffer k) and X2 = D_n^2 in pc[1]; the
@@ -702,6 +783,7 @@ static int recompute_segment(gcp_ctx *c, int n0, int n1) {
   Scalars s0{};   // traces of D_{n0}, as K1's reduction expects them
   s0.t1 = c->hist_host[(size_t)n0 * GCP_HIST_COLS + 1];
   s0.t2 = c->hist_host[(size_t)n0 * GCP_HIST_COLS + 2];
+  s0.prev_ddbar = INFINITY;
   *c->sc_host = s0;
   HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
   int pi = q.pi, k = 0;
@@ -755,18 +837,17 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
   Scalars s0{};
   s0.t1 = c->t1_0;
   s0.t2 = c->t2_0;
+  s0.prev_ddbar = INFINITY;
   *c->sc_host = s0;
   HIPCHK(c, hipMemcpyAsync(c->sc, c->sc_host, sizeof(Scalars), hipMemcpyHostToDevice, c->stream));
 
   const bool keep = c->opt.keep_iterates != 0;
   c->bwd_p = -1;
-  if (keep && c->opt.checkpoint_every < 2) {
-    const int st = store_iterate(c, 0, 0, prec);
-    if (st != GCP_OK) return st;
-  }
 
   const bool prof = c->opt.profile != 0;
-  const int max_launch = 2 * max_iter + 2;
+  // launches: K1 of updates 0..max_iter, K2 of 0..max_iter-1, plus at most
+  // sync_every - 1 void launches of each past the stop
+  const int max_launch = 2 * max_iter + 2 * c->opt.sync_every + 2;
   if (prof && (int)c->events.size() < 2 * max_launch) {
     for (int k = (int)c->events.size(); k < 2 * max_launch; ++k) {
       hipEvent_t e;
@@ -778,38 +859,64 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
   lg.prof = prof;
   GemmArgs g{};
   setup_gemm(c, g, 0);
+  g.status = &c->sc->status;   // launches past the device's stop do nothing
   const int ck = keep && c->opt.checkpoint_every >= 2 ? c->opt.checkpoint_every : 0;
   c->n_switch = -1;
 
-  int status = 0, n = 0;
-  for (;; ++n) {
-    const int k = c->cur;
-    if (ck && n % ck == 0) {
-      int st = save_checkpoint(c, n / ck, k, pi);
+  // Update n reads D_n from buffer n % 2 and writes D_{n+1} to the other.
+  // The decision to stop is taken on the device (k_reduce, before c_n is
+  // formed); the host enqueues sync_every updates at a time and reads the
+  // decision after each batch.  Until a precision schedule has switched, the
+  // host checks after every D^2, because the switch is decided there.
+  int status = 0, n = 0, syncs = 0;
+  for (;;) {
+    const bool per_step = c->nprec > 1 && pi == 0;
+    const int nb = per_step ? 1 : c->opt.sync_every;
+    bool stopped = false;
+    for (int q = 0; q < nb && n <= max_iter; ++q, ++n) {
+      const int k = n & 1;
+      if (ck && n % ck == 0) {
+        int st = save_checkpoint(c, n / ck, k, pi);
+        if (st != GCP_OK) return st;
+      }
+      int st = step_k1(c, g, pi, k, n, &lg);
+      if (st != GCP_OK) return st;
+      if (per_step) {
+        HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        ++syncs;
+        if (c->sc_host->status != 0) {
+          stopped = true;
+          break;
+        }
+        if (std::fabs(c->sc_host->t1 - c->sc_host->t2) <= c->opt.switch_ddbar) {
+          st = switch_precision(c, k);
+          if (st != GCP_OK) return st;
+          pi = 1;
+          prec = c->pc[1].prec;
+          c->n_switch = n;
+        }
+      }
+      // the iterate K2 reads, in the encoding it reads it (after a switch)
+      if (keep && !ck) {
+        st = store_iterate(c, n, k, prec);
+        if (st != GCP_OK) return st;
+      }
+      st = step_k2(c, g, pi, k, n, &lg);
       if (st != GCP_OK) return st;
     }
-    int st = step_k1(c, g, pi, k, n, &lg);
-    if (st != GCP_OK) return st;
-    HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    status = c->sc_host->status;
-    if (status != 0) break;
-    if (pi == 0 && c->nprec > 1 &&
-        std::fabs(c->sc_host->t1 - c->sc_host->t2) <= c->opt.switch_ddbar) {
-      st = switch_precision(c, k);
-      if (st != GCP_OK) return st;
-      pi = 1;
-      prec = c->pc[1].prec;
-      c->n_switch = n;
+    if (!stopped) {
+      HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost,
+                               c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      ++syncs;
     }
-    if (keep && !ck && n > 0) {
-      st = store_iterate(c, n, k, prec);
-      if (st != GCP_OK) return st;
-    }
-    st = step_k2(c, g, pi, k, n, &lg);
-    if (st != GCP_OK) return st;
-    c->cur = 1 - k;
+    if (c->sc_host->status != 0) break;
   }
+  status = c->sc_host->status;
+  n = c->sc_host->iter;
+  c->cur = n & 1;
   const int iters = n;
   if (keep) c->bwd_p = iters;
   // output D_p
@@ -834,6 +941,10 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
   int rc = GCP_OK;
   if (status == 2) rc = GCP_ERR_NOT_CONVERGED;
   if (status == 3) rc = GCP_ERR_BREAKDOWN;
+  if (status == 4) rc = GCP_STOPPED_AT_FLOOR;
+  // launches that did work: K1 of updates 0..p and K2 of 0..p-1 (any after
+  // them were enqueued past the stop and returned at once)
+  const int real = 2 * iters + 1 < lg.n ? 2 * iters + 1 : lg.n;
   if (res) {
     std::memset(res, 0, sizeof(*res));
     res->status = rc;
@@ -847,13 +958,20 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
     res->c_last = iters > 0 ? c->hist_host[(size_t)(iters - 1) * GCP_HIST_COLS + 4] : NAN;
     res->idem = std::sqrt(c->sc_host->omega);
     res->ms_total = std::chrono::duration<double, std::milli>(t_end - t_start).count();
-    res->gemm_launches = lg.n;
+    res->gemm_launches = real;
+    res->host_syncs = syncs;
     const double Md = (double)c->M;
-    res->gemm_flops = (double)lg.n * Md * Md * (Md + 1.0);
-    res->mfma_flops = lg.mfma_flops;
+    res->gemm_flops = (double)real * Md * Md * (Md + 1.0);
+    // issued MFMA flops: whole 128 x 128 tiles of the padded size times the
+    // split products; launches 0 .. 2 n_switch are in the first encoding
+    const double tile_fl = (double)c->ntiles * 2.0 * 128.0 * 128.0 * (double)c->Mp;
+    const int n0 = c->n_switch >= 0 ? 2 * c->n_switch + 1 : real;
+    const int first = n0 < real ? n0 : real;
+    res->mfma_flops = tile_fl * ((double)first * products(c->pc[0].prec) +
+                                 (double)(real - first) * products(c->pc[c->nprec - 1].prec));
     double ms = 0.0;
     if (prof) {
-      for (int k = 0; k < lg.n; ++k) {
+      for (int k = 0; k < real; ++k) {
         float t = 0.f;
         HIPCHK(c, hipEventElapsedTime(&t, c->events[2 * k], c->events[2 * k + 1]));
         ms += t;
@@ -861,9 +979,12 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
     }
     res->gemm_ms = ms;
   }
-  if (rc != GCP_OK)
-    c->err = status == 2 ? "gcp_purify: max_iter reached before the tolerance"
-                         : "gcp_purify: breakdown (c outside [0,1], Tr(D Dbar) < 0 or non-finite)";
+  if (rc == GCP_ERR_NOT_CONVERGED) c->err = "gcp_purify: max_iter reached before the tolerance";
+  if (rc == GCP_ERR_BREAKDOWN)
+    c->err = "gcp_purify: breakdown (c outside [0,1], Tr(D Dbar) <= 0 above the rounding floor, "
+             "or a non-finite value)";
+  if (rc == GCP_STOPPED_AT_FLOOR)
+    c->err = "gcp_purify: stopped at the rounding floor of the encoding above tol_ddbar";
   return rc;
 }
 

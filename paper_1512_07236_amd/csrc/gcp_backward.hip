@@ -180,8 +180,9 @@ __global__ __launch_bounds__(256) void k_bstore(const void *planes, const double
   using EF = Enc<PF>;
   using TF = typename EF::T;
   using TB = typename Enc<PB>::T;
-  const int64_t i = blockIdx.y;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  // rows on the x dimension of the grid (no 64K limit), 256 columns per block on y
+  const int64_t i = blockIdx.x;
+  const int64_t j = (int64_t)blockIdx.y * 256 + threadIdx.x;
   double x;
   if (i == j) {
     x = dg[i];
@@ -269,8 +270,9 @@ __global__ __launch_bounds__(256) void k_bsum(BwdInitArgs a) {
 template <int PB>
 __global__ __launch_bounds__(256) void k_bdh(BwdInitArgs a) {
   using TB = typename Enc<PB>::T;
-  const int64_t i = blockIdx.y;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  // rows on the x dimension of the grid (no 64K limit), 256 columns per block on y
+  const int64_t i = blockIdx.x;
+  const int64_t j = (int64_t)blockIdx.y * 256 + threadIdx.x;
   if (j >= a.M) return;
   double s = 0.0;
   if (a.beta != 0.0) {
@@ -291,7 +293,7 @@ __global__ __launch_bounds__(256) void k_bdh(BwdInitArgs a) {
 template <int PF>
 static hipError_t store_pf(int bprec, const void *planes, const double *dg, int64_t Mp, void *out,
                            hipStream_t st) {
-  const dim3 grid((unsigned)(Mp / 256), (unsigned)Mp);
+  const dim3 grid((unsigned)Mp, (unsigned)(Mp / 256));
   if (bprec == GCP_FP64)
     k_bstore<PF, GCP_FP64><<<grid, 256, 0, st>>>(planes, dg, Mp, out);
   else
@@ -350,7 +352,7 @@ hipError_t launch_bwd_kappa(const double *tpart, int n, double *kappa, hipStream
 }
 
 hipError_t launch_bwd_init(int bprec, const BwdInitArgs &a, hipStream_t st) {
-  const dim3 gout((unsigned)((a.M + 255) / 256), (unsigned)a.M);
+  const dim3 gout((unsigned)a.M, (unsigned)((a.M + 255) / 256));
   if (bprec == GCP_FP64) {
     k_bdot<GCP_FP64><<<(unsigned)a.Mp, 256, 0, st>>>(a);
     k_bsum<<<1, 256, 0, st>>>(a);

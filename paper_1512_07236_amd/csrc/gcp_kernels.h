@@ -10,9 +10,11 @@ namespace gcp {
 // Device-resident scalars of one solve (FP64 traces and the decision).
 struct Scalars {
   double t1, t2, t3, omega, c, step;
-  int32_t status;   // 0 continue, 1 converged, 2 max_iter reached, 3 breakdown
-  int32_t pad;
+  int32_t status;   // 0 continue, 1 converged, 2 max_iter reached, 3 breakdown,
+                    // 4 stopped at the rounding floor
+  int32_t iter;     // update at which status became non-zero
   double hstat[4];  // Gershgorin min, max, Tr H
+  double prev_ddbar;   // |Tr(D Dbar)| of the previous iterate (+inf before the first)
 };
 
 struct GemmArgs {
@@ -43,6 +45,9 @@ struct GemmArgs {
   double *part;        // row sums [nt][Mp]
   double *tpart;       // tile sums [ntiles]
   const double *coef;  // coef[0] = c_n (mode 1)
+  // non-NULL: the launch does nothing once *status is non-zero (the solve
+  // has stopped; later launches of a batch enqueued ahead are void)
+  const int32_t *status;
 };
 
 struct InitArgs {
@@ -67,6 +72,9 @@ struct RedArgs {
   int iter, max_iter;
   int pad;
   double tol_ddbar, tol_idem, N;
+  double floor_ddbar;  // rounding floor of |Tr(D Dbar)| of the encoding
+  int skip_if_stopped; // 1: do nothing once sc->status is non-zero
+  int pad2;
   Scalars *sc;
   double *hist;
 };

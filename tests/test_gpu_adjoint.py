@@ -82,7 +82,7 @@ def test_fp64_adjoint_matches_oracle(M, N, gap, seed):
     w = workloads.spectral(M, N, gap, seed)
     Gp = np.random.default_rng(seed + 100).standard_normal((M, M))
     dH, res, bres = gpu_grad(w, Gp, tol_ddbar=1e-6)
-    assert res.status == gcp.OK and bres.iters == res.iters
+    assert res.status in gcp.SUCCESS and bres.iters == res.iters
     ref = grad.adjoint(w.H, w.N, w.emin, w.emax, res.iters, Gp)
     err, tol = rel_max(dH, ref), fp64_tol(w, res.iters)
     log(f"  p={res.iters} err={err:.3e} tol={tol:.3e}")
@@ -220,6 +220,37 @@ def test_autograd_function_matches_oracle():
     assert rel_max(H.grad.cpu().numpy(), ref) <= fp64_tol(w, r.iters)
 
 
+def test_autograd_repeated_backward_and_side_stream():
+    """retain_iterates=True keeps the stored iterates for a second backward
+    through a retained graph (the same gradient, bitwise); without it the
+    second backward raises a clear error.  A solve started while a side
+    stream is current waits for that stream's work on H."""
+    w = workloads.spectral(256, 90, 0.1, 32)
+    P = to_gpu(workloads.sym_gaussian(256, 232))
+    H = to_gpu(w.H).requires_grad_(True)
+    D = gcp.purify_autograd(H, w.N, w.emin, w.emax, tol_ddbar=1e-6, retain_iterates=True)
+    loss = (D * P).sum()
+    g1, = torch.autograd.grad(loss, H, retain_graph=True)
+    g2, = torch.autograd.grad(loss, H)
+    assert torch.equal(g1, g2)
+    D = gcp.purify_autograd(H, w.N, w.emin, w.emax, tol_ddbar=1e-6)
+    loss = (D * P).sum()
+    torch.autograd.grad(loss, H, retain_graph=True)
+    with pytest.raises(RuntimeError, match="retain_iterates"):
+        torch.autograd.grad(loss, H)
+    side = torch.cuda.Stream()
+    Hd = to_gpu(w.H)
+    with gcp.Context(256, tol_ddbar=1e-6) as ctx:
+        ctx.init(Hd, w.N, w.emin, w.emax)
+        ref, _ = ctx.purify()
+        with torch.cuda.stream(side):
+            H2 = Hd * 1.0          # written on the side stream
+            ctx.init(H2, w.N, w.emin, w.emax)
+            D2, _ = ctx.purify()
+        side.synchronize()
+        assert torch.equal(D2, ref)
+
+
 def test_full_size_cubic_lattice_adjoint():
     """The 16 x 16 x 8 periodic lattice (M = 2048, N = 682) with
     L = Tr(D P), P symmetric Gaussian: FP64 and FP32 adjoints against the
@@ -269,7 +300,7 @@ def test_full_size_spectral_8192_against_daleckii_krein(precision, bwd, tol_ddba
     u = np.random.default_rng(33).standard_normal(w.M)
     dH, res, bres = gpu_grad(w, np.outer(u, u), precision=precision, bwd_precision=bwd,
                              tol_ddbar=tol_ddbar)
-    assert res.status == gcp.OK
+    assert res.status in gcp.SUCCESS
     rows = [0, 1, 777, 4095, 6000, 8191]
     ref = _dk_rows(w, u, rows)
     err = float(np.abs(dH[rows] - ref).max() / np.abs(ref).max())
@@ -286,7 +317,7 @@ def test_adjoint_through_a_precision_switch():
     Gp = workloads.sym_gaussian(384, 234)
     dH, res, _ = gpu_grad(w, Gp, precision="fp16x3", late_precision="fp64", switch_ddbar=1e-3,
                           tol_ddbar=1e-9)
-    assert res.status == gcp.OK
+    assert res.status in gcp.SUCCESS
     ref = grad.adjoint(w.H, w.N, w.emin, w.emax, res.iters, Gp)
     err = rel_max(dH, ref)
     log(f"  p={res.iters} err={err:.3e}")
@@ -296,12 +327,15 @@ def test_adjoint_through_a_precision_switch():
 @pytest.mark.parametrize("opts", [{}, {"bwd_precision": "fp32"},
                                   {"precision": "fp16x3", "late_precision": "fp64",
                                    "switch_ddbar": 1e-2, "tol_ddbar": 1e-9},
+                                  {"precision": "fp64", "late_precision": "fp16x3",
+                                   "switch_ddbar": 1e30, "tol_ddbar": 1e-6},
                                   {"hole": True}, {"max_iter": 0}])
 def test_checkpointed_backward_is_bitwise_the_kept_one(opts):
     """checkpoint_every = 3 and 5: every segment is recomputed from its
     checkpoint with the forward's kernels, so the gradient is bitwise the one
-    from kept iterates (including a precision switch inside a segment, the
-    hole recursion and a run with no update)."""
+    from kept iterates (including a precision switch inside a segment, one at
+    the first update, where the kept D_0 must be the re-encoded one that K2
+    reads, the hole recursion and a run with no update)."""
     w = workloads.spectral(384, 150, 0.1, 35)
     Gp = workloads.sym_gaussian(384, 235)
     o = {"tol_ddbar": 1e-6}

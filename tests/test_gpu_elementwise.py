@@ -1,0 +1,221 @@
+"""Element-wise parity of every encoding, one update at a time.
+
+For each encoding the GPU is run to a fixed number of updates n (max_iter=n,
+the solve is deterministic, so every run follows the same iterates).  Its
+returned D_n is its master iterate exactly (decoded planes + FP64 diagonal),
+and its history row n holds the traces and the coefficient c_n it used.  The
+oracle then applies one update of eq. (hpcp3) to that same D_n at that same
+c_n (``oracle.update_at``), in FP64, and the GPU's D_{n+1} must agree with it
+element by element within the bound derived from the encoding's unit
+roundoff and the FP32 accumulation scheme (``tests/bounds.py``).  T3 (the
+diagonal of D^3 summed, from the fused epilogue) and c_n are checked against
+the oracle's traces of D_n with bounds derived the same way; T2 against the
+FP64 sum of D_n o D_n.  The initial guess is checked against the oracle's
+D_0 within one encoding rounding.
+
+Sizes: M = 640 and 1000 (padded to 768 and 1024: ragged tails, every tile
+pair split along K, diagonal-tile mirrors) and M = 3900 (padded to 4096:
+256 whole pairs plus a K-split tail of 16 pairs, the launch shapes of the
+full-size runs).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from bounds import c_bound, max_abs_bound, step_bounds, encoding
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1512_07236_amd as gcp  # noqa: E402
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _oracle(oracle_lib):
+    return oracle_lib
+
+
+def gpu_iterates(w, precision, steps, **opts):
+    """D_n for n in steps (FP64 copies of the GPU's master iterates) and the
+    history of the longest run (rows 0..max(steps)+1)."""
+    H = torch.from_numpy(np.ascontiguousarray(w.H)).cuda()
+    out = {}
+    hist = None
+    with gcp.Context(w.M, precision=precision, tol_ddbar=0.0, tol_idem=0.0,
+                     max_iter=max(steps) + 1, **opts) as ctx_last:
+        ctx_last.init(H, w.N, w.emin, w.emax)
+        D, res = ctx_last.purify()
+        hist = res.history
+        out[max(steps) + 1] = D.cpu().numpy()
+    for n in steps:
+        with gcp.Context(w.M, precision=precision, tol_ddbar=0.0, tol_idem=0.0, max_iter=n,
+                         **opts) as ctx:
+            ctx.init(H, w.N, w.emin, w.emax)
+            D, res = ctx.purify()
+            assert res.status == gcp.ERR_NOT_CONVERGED and res.iters == n
+            # the same iterates: rows before n are bitwise those of the longest run
+            assert np.array_equal(res.history[:n], hist[:n], equal_nan=True)
+            out[n] = D.cpu().numpy()
+    return out, hist
+
+
+def check_step(Dn, Dn1, row, precision, fold_every=0, label=""):
+    """One update: the GPU's D_{n+1} against the oracle's update of D_n at
+    the GPU's c_n; T2, T3 and c_n against the oracle's traces of D_n."""
+    n, t1, t2, t3, c = row[0], row[1], row[2], row[3], row[4]
+    ref, (o1, o2, o3, oc) = oracle.update_at(Dn, c)
+    b = step_bounds(Dn, c, precision, fold_every)
+    diff = np.abs(Dn1 - ref)
+    ratio = diff / b["dD"]
+    k = np.unravel_index(int(np.argmax(ratio)), ratio.shape)
+    # the statistical bound is the tighter one; the worst case always holds
+    dc_det = c_bound(o1, o2, o3, b["T1"], b["T2"], b["T3_det"])
+    dc_sig = c_bound(o1, o2, o3, b["T1"], b["T2"], b["T3_sig"])
+    log(f"  {label} n={int(n)}: max|dD|={diff.max():.2e} worst ratio {ratio.max():.3f} at {k} "
+        f"(bound {b['dD'][k]:.2e}); dT2={abs(t2 - o2):.2e}/{b['T2']:.1e} "
+        f"dT3={abs(t3 - o3):.2e}/{b['T3_sig']:.1e} (det {b['T3_det']:.1e}) "
+        f"dc={abs(c - oc):.2e}/{dc_sig:.1e}")
+    assert np.all(diff <= b["dD"]), (label, int(n), k, diff[k], b["dD"][k])
+    assert abs(t1 - o1) <= b["T1"]
+    assert abs(t2 - o2) <= b["T2"]
+    assert abs(t3 - o3) <= b["T3_sig"] and abs(t3 - o3) <= b["T3_det"]
+    assert abs(c - oc) <= dc_sig
+    assert abs(c - oc) <= dc_det
+
+
+def check_guess(w, D0, precision):
+    ref, _, _ = oracle.initial_guess(w.H, w.N, w.emin, w.emax)
+    u_enc, a_enc, _ = encoding(precision)
+    off = ~np.eye(w.M, dtype=bool)
+    tol = np.where(off, u_enc * np.abs(ref) + a_enc, 0.0) + 8 * 2.0 ** -53 * (np.abs(ref) + 1.0)
+    assert np.all(np.abs(D0 - ref) <= tol)
+
+
+ENCODINGS = ["fp64", "fp32", "bf16x3", "fp16x3", "bf16x6", "bf16", "fp16"]
+
+
+@pytest.mark.parametrize("precision", ENCODINGS)
+@pytest.mark.parametrize("M,N", [(640, 234), (1000, 377)])
+def test_one_update_at_a_time_small(M, N, precision):
+    w = workloads.spectral(M, N, gap=0.1, seed=M + 7)
+    log(f"[gpu] element-wise {precision} M={M} N={N}")
+    steps = [0, 1, 2]
+    it, hist = gpu_iterates(w, precision, steps)
+    check_guess(w, it[0], precision)
+    for n in steps:
+        check_step(it[n], it[n + 1], hist[n], precision, label=f"{precision} M={M}")
+
+
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x6", "fp32"])
+def test_one_update_at_a_time_whole_pairs_and_tail(precision):
+    """M = 3900 (padded 4096): the 16-bit kernel computes 256 whole tile
+    pairs and splits the remaining 16 along K; the FP32 kernel 528 tiles."""
+    w = workloads.spectral(3900, 1500, gap=0.1, seed=3900)
+    log(f"[gpu] element-wise {precision} M=3900")
+    steps = [0, 1]
+    it, hist = gpu_iterates(w, precision, steps)
+    check_guess(w, it[0], precision)
+    for n in steps:
+        check_step(it[n], it[n + 1], hist[n], precision, label=f"{precision} M=3900")
+
+
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x6"])
+def test_late_updates_near_convergence(precision):
+    """The last updates before the stop, where Tr(D Dbar) is small and c_n
+    is most sensitive to the traces."""
+    w = workloads.spectral(1000, 377, gap=0.1, seed=1007)
+    s = oracle.scalar_map(w.lam, w.N, w.emin, w.emax, mu=np.trace(w.H) / w.M, tol_ddbar=1e-6)
+    p = s["iters"]
+    steps = [p - 3, p - 2]
+    log(f"[gpu] element-wise late updates {precision} M=1000 p={p} steps={steps}")
+    it, hist = gpu_iterates(w, precision, steps)
+    for n in steps:
+        check_step(it[n], it[n + 1], hist[n], precision, label=f"{precision} late")
+
+
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x6"])
+def test_fold_periods_element_wise(precision):
+    """Fold periods 1 and 'never' change only the rounding, within the bound
+    of their own accumulation scheme."""
+    w = workloads.spectral(1000, 377, gap=0.1, seed=11)
+    for fold in (1, 1000):
+        it, hist = gpu_iterates(w, precision, [1], fold_every=fold)
+        check_step(it[1], it[2], hist[1], precision, fold_every=fold,
+                   label=f"{precision} fold={fold}")
+
+
+@pytest.fixture(scope="module")
+def config3():
+    log("[gpu] generating workload 3 (M = 8192, N = 3000, gap 0.05)")
+    w = workloads.config(3)
+    ref = oracle.projector_from_spectrum(w.Q, w.lam, w.N)
+    return w, ref
+
+
+@pytest.mark.parametrize("precision,tol_ddbar", [("fp16x3", 1e-5), ("bf16x6", 1e-5)])
+def test_full_size_max_abs_and_one_step_traces(config3, precision, tol_ddbar):
+    """M = 8192: (a) no element of D - D_ref is an outlier of the error
+    distribution (a wrongly stored or mirrored element would be); (b) at the
+    first update and at the last one before the stop, T2, T3 and c_n equal
+    the oracle's traces of the GPU's own iterate within the statistical
+    bound (6 sigma)."""
+    w, ref = config3
+    H = torch.from_numpy(w.H).cuda()
+    with gcp.Context(w.M, precision=precision, tol_ddbar=tol_ddbar) as ctx:
+        ctx.init(H, w.N, w.emin, w.emax)
+        D, res = ctx.purify()
+        Dh = D.cpu().numpy()
+    assert res.status == gcp.OK
+    E = Dh - ref
+    fro = float(np.linalg.norm(E))
+    mx = float(np.abs(E).max())
+    bound = max_abs_bound(fro, w.M)
+    log(f"  {precision}: iters={res.iters} err={fro / math.sqrt(w.M):.3e} max|E|={mx:.3e} "
+        f"(outlier bound {bound:.3e})")
+    assert fro / math.sqrt(w.M) <= 1e-6
+    assert mx <= bound
+    del E, D
+    p = res.iters
+    hist = res.history
+    for n in (0, p - 1):
+        with gcp.Context(w.M, precision=precision, tol_ddbar=0.0, max_iter=n) as ctx:
+            ctx.init(H, w.N, w.emin, w.emax)
+            Dn, r = ctx.purify()
+            Dn = Dn.cpu().numpy()
+        o1, o2, o3, oc = oracle.power_traces(Dn)
+        t1, t2, t3, c = hist[n, 1], hist[n, 2], hist[n, 3], hist[n, 4]
+        # statistical bound of T3 at this size (the worst case is far looser)
+        M = w.M
+        from bounds import accumulation_kappa, unit, U64
+        u_enc, a_enc, u_drop = encoding(precision)
+        A = np.abs(Dn)
+        P1 = A @ A
+        X2 = Dn @ Dn
+        D2sq = Dn * Dn
+        off = ~np.eye(M, dtype=bool)
+        kappa = accumulation_kappa(M, precision)
+        var = ((2 * unit(precision)) ** 2 * kappa * (1.01 * P1) ** 2 / 3
+               + (u_enc * X2) ** 2 / 3 + (u_drop ** 2 / 9) * (D2sq @ D2sq) + a_enc ** 2 / 3)
+        dT3 = 6.0 * math.sqrt(2.0 * float((D2sq * var)[off].sum())) \
+            + 4 * M * U64 * float((np.abs(X2) * A).sum()) + 2 * M * U64 * float(np.diag(P1) @ np.diag(A))
+        dT2 = 4 * M * U64 * float(D2sq.sum())
+        dT1 = 4 * M * U64 * float(np.abs(np.diag(Dn)).sum())
+        dc = c_bound(o1, o2, o3, dT1, dT2, dT3)
+        log(f"  n={n}: Tr(D Dbar)={o1 - o2:.3e} dT2={abs(t2 - o2):.2e}/{dT2:.1e} "
+            f"dT3={abs(t3 - o3):.2e}/{dT3:.1e} dc={abs(c - oc):.2e}/{dc:.1e}")
+        assert abs(t1 - o1) <= dT1 and abs(t2 - o2) <= dT2
+        assert abs(t3 - o3) <= dT3
+        assert abs(c - oc) <= dc
+        del Dn, A, P1, X2, D2sq, var

@@ -124,7 +124,7 @@ def test_precisions_trace_exact_and_error_bounded(precision):
     # rounding noise and leaves [0, 1] (reported as a breakdown)
     tol = TOL_DDBAR[precision]
     D, res = run_gpu(w, precision, tol_ddbar=tol)
-    assert res.status == gcp.OK, res
+    assert res.status in gcp.SUCCESS, res
     assert np.abs(res.col("t1") - w.N).max() < 1e-10
     assert abs(np.trace(D) - w.N) < 1e-10
     err = rel_err(D, oracle.projector_from_spectrum(w.Q, w.lam, w.N))
@@ -143,7 +143,7 @@ def test_fold_period_changes_only_rounding(precision, fold):
     w = workloads.spectral(512, 200, gap=0.1, seed=5)
     ref = oracle.projector_from_spectrum(w.Q, w.lam, w.N)
     D, r = run_gpu(w, precision, tol_ddbar=TOL_DDBAR[precision], fold_every=fold)
-    assert r.status == gcp.OK
+    assert r.status in gcp.SUCCESS
     e = rel_err(D, ref)
     log(f"  {precision} fold={fold}: err {e:.3e}")
     assert e < 2 * ERR_TOL[precision] and abs(np.trace(D) - w.N) < 1e-10
@@ -264,27 +264,35 @@ def test_full_size_spectral_8192(config3, precision, tol_ddbar, err_tol):
     err = rel_err(D, ref)
     log(f"  {precision}: iters={res.iters} (map {s['iters']}) err={err:.3e} "
         f"trace err={abs(np.trace(D) - w.N):.2e} ms={res.ms_total:.1f}")
-    assert res.status == gcp.OK
+    assert res.status in gcp.SUCCESS
     assert np.abs(res.col("t1") - w.N).max() < 1e-10
     assert err < err_tol
+    assert abs(res.iters - s["iters"]) <= (0 if precision == "fp64" else 1)
+    if precision != "fp64":
+        # the split encodings' c_n and T3 are checked one update at a time
+        # against the oracle's traces of the GPU's own iterate
+        # (tests/test_gpu_elementwise.py); along the whole trajectory their
+        # iterates drift from the exact ones by the accumulated rounding.
+        return
     n = min(res.iters, s["iters"])
     ddbar = (res.col("t1") - res.col("t2"))[:n]
-    # c_n = (T2 - T3)/(T1 - T2): an absolute error e in the traces of the
-    # iterate moves c_n by about e/(T1 - T2).  FP64: the traces (~N = 3000)
-    # are tree sums over 8192 rows; the top levels dominate, each adding
-    # ~2^-53 x 3000 x 2^(-k/2) at depth k, ~1.1e-12 RMS per trace and
-    # ~1.5e-12 for the difference, so e = 4e-12 (3 sigma); measured e up
-    # to 1.6e-12 and |Tr D - N| = 3.6e-12 at this size.  The split
-    # encodings carry ~2^-22 relative error per element, which measured
-    # as e ~ 8e-7 (bound: 1e-5).
-    ctol, cnum = (1e-11, 4e-12) if precision == "fp64" else (1e-4, 1e-5)
+    # FP64: the GPU and the eigenvalue map follow the same iterates to FP64
+    # rounding.  c_n = (T2 - T3)/(T1 - T2) moves by e/(T1 - T2) for an
+    # absolute error e of the traces.  The traces (~N = 3000) are tree sums
+    # over 8192 rows; the top levels dominate, each adding ~2^-53 x 3000 x
+    # 2^(-k/2) at depth k: ~1.1e-12 RMS per trace and ~1.5e-12 for the
+    # difference, so e = 4e-12 (3 sigma).
+    ctol, cnum = 1e-11, 4e-12
     dc = np.abs(res.col("c")[:n] - s["c"][:n])
     ratio = dc / (ctol + cnum / np.abs(ddbar))
     k = int(np.argmax(ratio))
-    log(f"  c_n: worst n={k} dc={dc[k]:.3e} ddbar={ddbar[k]:.3e} ratio={ratio[k]:.3f}; "
-        + " ".join(f"{x:.2e}" for x in dc * np.abs(ddbar)))
+    log(f"  c_n: worst n={k} dc={dc[k]:.3e} ddbar={ddbar[k]:.3e} ratio={ratio[k]:.3f}")
     assert np.all(ratio <= 1.0)
-    assert abs(res.iters - s["iters"]) <= (0 if precision == "fp64" else 1)
+    # T3 of every iterate against the map's power sum: one trace's 3 sigma
+    # (3.3e-12) is below e
+    dt3 = np.abs(res.col("t3")[:n] - s["t3"][:n])
+    log(f"  T3: max |dT3| = {dt3.max():.3e}")
+    assert np.all(dt3 <= cnum)
 
 
 # ------------------------------------------------------- precision schedule
@@ -333,7 +341,7 @@ def test_schedule_switch(early, late, switch, err_lo, err_hi):
                       tol_ddbar=tol, max_iter=60)
     err = rel_err(D, ref)
     log(f"  {early}->{late}: iters={res.iters} err={err:.3e} idem={res.idem:.2e}")
-    assert res.status == gcp.OK
+    assert res.status in gcp.SUCCESS
     assert np.abs(res.col("t1") - w.N).max() < 1e-10
     assert err_lo <= err < err_hi
     if late == "fp64":
@@ -353,6 +361,6 @@ def test_full_size_spectral_4096_fp64_vs_fp32(precision, tol_ddbar, err_tol):
     D, res = run_gpu(w, precision, tol_ddbar=tol_ddbar)
     err = rel_err(D, ref)
     log(f"  {precision}: iters={res.iters} err={err:.3e} ms={res.ms_total:.1f}")
-    assert res.status == gcp.OK
+    assert res.status in gcp.SUCCESS
     assert np.abs(res.col("t1") - w.N).max() < 1e-10
     assert err < err_tol

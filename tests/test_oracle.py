@@ -109,6 +109,47 @@ def test_eigenvalues_follow_scalar_map():
     assert np.abs(Q.T @ D1 @ Q - np.diag(fx)).max() < 1e-13
 
 
+@pytest.mark.parametrize("method,c", [("hpcp", 0.3), ("hpcp", 0.8), ("pmcp", 0.2), ("pmcp", 0.7)])
+def test_update_at_given_c_follows_the_eigenvalue_map(method, c):
+    """update_at(D, c) at a coefficient c chosen from outside: the eigenvalues
+    of D = Q diag(x) Q^T map by eq. (hpcp3) on numbers, x + 2(x^2(1-x) -
+    c x(1-x)) (or eqs. (pm1a)/(pm1b) on numbers for PMCP), the eigenvectors
+    are kept, the returned traces are the power sums of x, and the trace
+    moves by exactly 2(T2 - T3) - 2c(T1 - T2) for HPCP (zero only at the
+    coefficient the recursion forms itself)."""
+    M = 14
+    x = np.random.default_rng(21).uniform(0.02, 0.98, M)
+    D, Q = rand_sym_spectrum(M, x, 9)
+    D1, (t1, t2, t3, c_own) = oracle.update_at(D, c, method=method)
+    if method == "hpcp":
+        fx = x + 2 * (x * x * (1 - x) - c * x * (1 - x))
+    elif c <= 0.5:
+        fx = ((1 - 2 * c) * x + (1 + c) * x * x - x ** 3) / (1 - c)
+    else:
+        fx = ((1 + c) * x * x - x ** 3) / c
+    assert np.abs(Q.T @ D1 @ Q - np.diag(fx)).max() < 1e-13
+    assert abs(t1 - x.sum()) < 1e-13 and abs(t2 - (x ** 2).sum()) < 1e-13
+    assert abs(t3 - (x ** 3).sum()) < 1e-13
+    assert abs(c_own - ((x ** 2).sum() - (x ** 3).sum()) / (x.sum() - (x ** 2).sum())) < 1e-13
+    if method == "hpcp":
+        assert abs(np.trace(D1) - t1 - (2 * (t2 - t3) - 2 * c * (t1 - t2))) < 1e-12
+    # c = NaN applies the recursion's own coefficient: one step of purify_from
+    D1n, _ = oracle.update_at(D, float("nan"), method=method)
+    r = oracle.purify_from(D, int(round(x.sum())), tol_ddbar=-np.inf, tol_idem=-np.inf,
+                           max_iter=1, method=method)
+    assert np.abs(D1n - r.D).max() < 1e-14
+
+
+def test_power_traces_are_power_sums_of_the_spectrum():
+    M = 30
+    x = np.random.default_rng(22).uniform(-0.1, 1.1, M)
+    D, _ = rand_sym_spectrum(M, x, 10)
+    t1, t2, t3, c = oracle.power_traces(D)
+    s1, s2, s3 = x.sum(), (x ** 2).sum(), (x ** 3).sum()
+    assert abs(t1 - s1) < 1e-12 and abs(t2 - s2) < 1e-12 and abs(t3 - s3) < 1e-12
+    assert abs(c - (s2 - s3) / (s1 - s2)) < 1e-12
+
+
 # ----------------------------------------------------------------- invariants
 
 def test_trace_conserved_every_step():
