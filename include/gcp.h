@@ -249,6 +249,32 @@ typedef struct {
 int gcp_verify(gcp_ctx *ctx, const void *D, int32_t dtype, int64_t ldd, const double *H,
                int64_t ldh, gcp_verify_result *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the whole
+ * solve of gcp_create + gcp_init + gcp_purify in one call that allocates
+ * nothing.  Its workspace is a static device array of
+ * GCP_STATIC_SCRATCH_BYTES, one per GPU, held by the library from its first
+ * use on that GPU until the process ends; M is limited to GCP_STATIC_MAX_M.
+ *   H, ldh, N, emin, emax   as for gcp_init (device FP64 H, NaN bounds ->
+ *                           Gershgorin);
+ *   opt                     as for gcp_create (NULL = defaults); keep_iterates
+ *                           and profile must be 0 (they would allocate);
+ *   D, dtype, ldd, out      as for gcp_purify (D device, out may be NULL);
+ *   stream                  a hipStream_t as void* (NULL = default stream).
+ * Returns the status gcp_purify would (OK, STOPPED_AT_FLOOR, NOT_CONVERGED,
+ * BREAKDOWN), INVALID_ARG for M > GCP_STATIC_MAX_M or the options above, or
+ * the errors of gcp_init; the text is in gcp_last_error(NULL).  Every call
+ * on a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * host threads, other streams) race and must be serialised by the caller.
+ * The iterates and D are bitwise those of gcp_create + gcp_init +
+ * gcp_purify with the same options on the same GPU (the same kernels and
+ * launch configuration). */
+#define GCP_STATIC_MAX_M 1024
+#define GCP_STATIC_SCRATCH_BYTES (48u << 20)
+int gcp_purify_static(const double *H, int64_t ldh, int64_t M, int64_t N, double emin,
+                      double emax, const gcp_options *opt, void *D, int32_t dtype, int64_t ldd,
+                      void *stream, gcp_result *out);
+
 /* Per-iterate history of the last gcp_purify: GCP_HIST_COLS doubles per row,
  *   [n, Tr D, Tr D^2, Tr D^3, c_n, Omega = ||D^2-D||_F^2, gamma_n = (1-2c_n)/3,
  *    L_n = Omega - gamma_n (3 Tr D^2 - 2 Tr D^3 - N) (eq. mcw4b), ||D_{n+1} - D_n||_F]

@@ -136,6 +136,9 @@ def load_library() -> ctypes.CDLL:
     L.gcp_get_init_scalars.restype = ctypes.c_int
     L.gcp_last_error.argtypes = [vp]
     L.gcp_last_error.restype = ctypes.c_char_p
+    L.gcp_purify_static.argtypes = [vp, i64, i64, i64, dbl, dbl, ctypes.POINTER(Options), vp, i32,
+                                    i64, vp, ctypes.POINTER(CResult)]
+    L.gcp_purify_static.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -341,6 +344,32 @@ def purify(H, N: int, emin: float = math.nan, emax: float = math.nan, precision=
     with Context(H.shape[0], precision=precision, **options) as ctx:
         ctx.init(H, N, emin, emax)
         return ctx.purify(out=out)
+
+
+STATIC_MAX_M = 1024
+
+
+def purify_static(H, N: int, emin: float = math.nan, emax: float = math.nan, out=None,
+                  precision="fp64", **options):
+    """gcp_purify_static: the whole solve without any device allocation by the
+    library (workspace in its static per-GPU array, M <= STATIC_MAX_M).
+    Returns (D, status, iters) where D is `out` (or a new tensor allocated
+    here by torch, before the call)."""
+    import torch
+    L = load_library()
+    M = H.shape[0]
+    if out is None:
+        out = torch.empty((M, M), dtype=torch.float64, device=H.device)
+    o = default_options()
+    o.precision = int(Precision.parse(precision))
+    for k, v in options.items():
+        setattr(o, k, v)
+    r = CResult()
+    st = L.gcp_purify_static(ctypes.c_void_p(H.data_ptr()), H.stride(0), M, int(N), float(emin),
+                             float(emax), ctypes.byref(o), ctypes.c_void_p(out.data_ptr()),
+                             DTYPE_F64 if out.dtype == torch.float64 else DTYPE_F32,
+                             out.stride(0), ctypes.c_void_p(_stream_handle(None)), ctypes.byref(r))
+    return out, st, r
 
 
 def _autograd_function():

@@ -8,6 +8,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -61,6 +62,9 @@ int products(int prec) {
 }  // namespace
 
 struct gcp_ctx {
+  // a solve of gcp_purify_static: workspace carved from the static array,
+  // D_0 built in place in Dp[0], no host-side history kept
+  bool one_shot = false;
   int64_t M = 0, Mp = 0;
   int nt = 0, ntiles = 0, ntpart = 0, nred = 0;
   gcp_options opt{};
@@ -830,10 +834,12 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
 
   // start from D_0
   c->cur = 0;
-  HIPCHK(c, hipMemcpyAsync(c->Dp[0], c->D0p, plane_bytes(c), hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->dg[0], c->dg0, vec, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->rD[0], c->rD0, vec, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->d2[0], c->d20, vec, hipMemcpyDeviceToDevice, c->stream));
+  if (c->D0p != c->Dp[0]) {   // (a one-shot solve builds D_0 in place)
+    HIPCHK(c, hipMemcpyAsync(c->Dp[0], c->D0p, plane_bytes(c), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->dg[0], c->dg0, vec, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->rD[0], c->rD0, vec, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d2[0], c->d20, vec, hipMemcpyDeviceToDevice, c->stream));
+  }
   Scalars s0{};
   s0.t1 = c->t1_0;
   s0.t2 = c->t2_0;
@@ -932,10 +938,17 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
   oa.hole = c->opt.hole;
   HIPCHK(c, launch_output(prec, oa, c->stream));
   c->hist_rows = iters + 1;
-  c->hist_host.assign((size_t)c->hist_rows * GCP_HIST_COLS, NAN);
-  HIPCHK(c, hipMemcpyAsync(c->hist_host.data(), c->hist,
-                           c->hist_host.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  double c_last = NAN;
+  if (!c->one_shot) {
+    c->hist_host.assign((size_t)c->hist_rows * GCP_HIST_COLS, NAN);
+    HIPCHK(c, hipMemcpyAsync(c->hist_host.data(), c->hist, c->hist_host.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+  } else if (iters > 0) {   // only c of the last update
+    HIPCHK(c, hipMemcpyAsync(&c_last, c->hist + (size_t)(iters - 1) * GCP_HIST_COLS + 4,
+                             sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (!c->one_shot && iters > 0) c_last = c->hist_host[(size_t)(iters - 1) * GCP_HIST_COLS + 4];
   const auto t_end = std::chrono::steady_clock::now();
 
   int rc = GCP_OK;
@@ -955,7 +968,7 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
       res->t1 = (double)c->M - c->sc_host->t1;
       res->t2 = (double)c->M - 2.0 * c->sc_host->t1 + c->sc_host->t2;
     }
-    res->c_last = iters > 0 ? c->hist_host[(size_t)(iters - 1) * GCP_HIST_COLS + 4] : NAN;
+    res->c_last = c_last;
     res->idem = std::sqrt(c->sc_host->omega);
     res->ms_total = std::chrono::duration<double, std::milli>(t_end - t_start).count();
     res->gemm_launches = real;
@@ -1203,4 +1216,94 @@ extern "C" int gcp_get_history(const gcp_ctx *c, double *rows, int32_t max_rows,
     if (n > 0) std::memcpy(rows, c->hist_host.data(), (size_t)n * GCP_HIST_COLS * sizeof(double));
   }
   return GCP_OK;
+}
+
+// ------------------------------------------------ solve without allocation
+// Workspace of gcp_purify_static: one copy per GPU, held until the process
+// ends.  In host code `scratch` names a host-side stand-in; its device
+// address on each GPU comes from hipGetSymbolAddress (kept per device) and is
+// the only form in which host code uses it.
+static __device__ __align__(256) unsigned char scratch[GCP_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array (the device must be current).
+int scratch_address(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    g_create_error = "gcp_purify_static: device index out of range";
+    return GCP_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      g_create_error.set("gcp_purify_static: hipGetSymbolAddress(scratch)", hipGetErrorString(e));
+      return GCP_ERR_HIP;
+    }
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return GCP_OK;
+}
+}  // namespace
+
+extern "C" int gcp_purify_static(const double *H, int64_t ldh, int64_t M, int64_t N, double emin,
+                                 double emax, const gcp_options *opt, void *D, int32_t dtype,
+                                 int64_t ldd, void *stream, gcp_result *out) {
+  gcp_options o;
+  if (opt) o = *opt; else gcp_options_default(&o);
+  int st = check_options(o, M, g_create_error);
+  if (st != GCP_OK) return st;
+  if (M > GCP_STATIC_MAX_M) {
+    std::snprintf(g_create_error.buf, sizeof(g_create_error.buf),
+                  "gcp_purify_static: M = %lld exceeds GCP_STATIC_MAX_M = %d", (long long)M,
+                  GCP_STATIC_MAX_M);
+    return GCP_ERR_INVALID_ARG;
+  }
+  if (o.keep_iterates || o.profile) {
+    g_create_error = "gcp_purify_static: keep_iterates and profile need allocations; use gcp_create";
+    return GCP_ERR_INVALID_ARG;
+  }
+  gcp_ctx c;   // on the stack; its host containers stay empty
+  c.one_shot = true;
+  setup_ctx(&c, M, o, stream);
+  void *base = nullptr;
+  st = scratch_address(c.device, &base);
+  if (st != GCP_OK) return st;
+  size_t off = 0;
+  for_each_buffer(&c, true, [&](void **p, size_t bytes) {
+    off = (off + 255) / 256 * 256;
+    *p = (off + bytes <= GCP_STATIC_SCRATCH_BYTES) ? (void *)((char *)base + off) : nullptr;
+    off += bytes;
+  });
+  if (off > GCP_STATIC_SCRATCH_BYTES) {
+    std::snprintf(g_create_error.buf, sizeof(g_create_error.buf),
+                  "gcp_purify_static: the workspace of M = %lld needs %zu bytes, more than the "
+                  "static %u (lower max_iter)", (long long)M, off, GCP_STATIC_SCRATCH_BYTES);
+    return GCP_ERR_INVALID_ARG;
+  }
+  c.D0p = c.Dp[0];
+  c.dg0 = c.dg[0];
+  c.rD0 = c.rD[0];
+  c.d20 = c.d2[0];
+  Scalars host_sc{};
+  c.sc_host = &host_sc;
+  // the array keeps the previous call's contents: the arrival counters and
+  // the X2 diagonal residuals must start at zero
+  int ntail, smax;
+  split_tail(&c, ntail, smax);
+  if (launch_zero(c.g16_cnt, ntail, c.stream) != hipSuccess ||
+      launch_zero(c.counter, 1, c.stream) != hipSuccess ||
+      launch_zero(c.s2, 2 * c.Mp, c.stream) != hipSuccess) {
+    g_create_error = "gcp_purify_static: clearing the workspace failed";
+    return GCP_ERR_HIP;
+  }
+  st = gcp_init(&c, H, ldh, N, emin, emax);
+  if (st == GCP_OK) st = gcp_purify(&c, D, dtype, ldd, out);
+  if (st != GCP_OK) g_create_error = c.err.c_str();
+  return st;
 }

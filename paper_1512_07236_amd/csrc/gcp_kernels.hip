@@ -1713,6 +1713,19 @@ hipError_t launch_hdev(const double *H, int64_t ldh, int64_t M, int64_t Mp, doub
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_zero(uint32_t *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = 0u;
+}
+
+hipError_t launch_zero(void *p, int64_t nwords, hipStream_t st) {
+  if (!p || nwords <= 0) return hipSuccess;
+  int64_t nb = (nwords + 255) / 256;
+  if (nb > 1024) nb = 1024;
+  k_zero<<<(unsigned)nb, 256, 0, st>>>((uint32_t *)p, nwords);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce(const RedArgs &a, hipStream_t st) {
   k_reduce<<<(unsigned)((a.Mp + 63) / 64), 256, 0, st>>>(a);
   return hipGetLastError();
