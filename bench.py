@@ -138,12 +138,22 @@ COPY_BYTES = 1 << 30
 
 
 def copy_calibration() -> None:
-    """A plain device-to-device copy of exactly COPY_BYTES (read COPY_BYTES,
-    write COPY_BYTES): the yardstick for the memory-traffic counters."""
+    """The yardsticks for the memory-traffic counters: a plain device copy of
+    exactly COPY_BYTES (reads and writes COPY_BYTES; the reference for
+    WRITE_SIZE, whose stores are ordinary global stores), and the library's
+    gcp_stream_lds over COPY_BYTES (reads them with the product kernel's own
+    global-to-LDS loads and writes nothing; the reference for FETCH_SIZE)."""
+    import ctypes
     import torch
+    import paper_1512_07236_amd as gcp
     src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
+    torch.cuda.synchronize()
+    L = gcp.load_library()
+    st = L.gcp_stream_lds(ctypes.c_void_p(src.data_ptr()), COPY_BYTES,
+                          ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == gcp.OK, st
     torch.cuda.synchronize()
 
 
@@ -163,23 +173,31 @@ def summarize_pmc(precision: str, scale: int, fetch_dir: str, write_dir: str) ->
     import paper_1512_07236_amd as gcp
     prec = gcp.Precision.parse(precision)
     M = 8192 // scale
-    kname = "k_gemm16" if gcp.PRODUCTS[prec] > 1 or prec in (gcp.Precision.BF16, gcp.Precision.FP16) else "k_gemm"
+    kname = "k_gemm16" if gcp.MFMA_DTYPE[prec] in ("fp16", "bf16") else "k_gemm"
     tag = f"gemm_{prec.name.lower()}_M{M}"
     out = {"kernel": f"{kname}<{int(prec)}>", "workload": f"M={M}", "precision": prec.name.lower()}
     for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = [r for r in _counter_rows(d) if r["Counter_Name"] == name]
-        kern = [float(r["Counter_Value"]) for r in rows if f"{kname}<{int(prec)}>" in r["Kernel_Name"]]
-        # the calibration copy: FETCH_SIZE reads about half of its true bytes
-        # (WRITE_SIZE all of them), so accept copy kernels above a quarter
-        copy = [float(r["Counter_Value"]) for r in rows
-                if ("copy" in r["Kernel_Name"].lower() or "elementwise" in r["Kernel_Name"].lower())
-                and float(r["Counter_Value"]) * 1024 > 0.25 * COPY_BYTES]
-        if not kern or not copy:
-            print(f"no {name} rows for the kernel or the copy in {d}", file=sys.stderr)
+        # launches that did work (a solve's launches past its stop do nothing)
+        kern = [float(r["Counter_Value"]) for r in rows
+                if f"{kname}<{int(prec)}>" in r["Kernel_Name"] and float(r["Counter_Value"]) > 1024]
+        # yardsticks of known size: the global-to-LDS stream for FETCH_SIZE
+        # (the product kernel's load type), the plain copy for WRITE_SIZE
+        if name == "FETCH_SIZE":
+            ref = [float(r["Counter_Value"]) for r in rows if "k_stream_lds" in r["Kernel_Name"]]
+            ref_name = "gcp_stream_lds (global_load_lds, 128-byte rows)"
+        else:
+            ref = [float(r["Counter_Value"]) for r in rows
+                   if ("copy" in r["Kernel_Name"].lower() or "elementwise" in r["Kernel_Name"].lower())
+                   and float(r["Counter_Value"]) * 1024 > 0.25 * COPY_BYTES]
+            ref_name = "device copy"
+        if not kern or not ref:
+            print(f"no {name} rows for the kernel or the yardstick in {d}", file=sys.stderr)
             return 1
-        factor = (max(copy) * 1024) / COPY_BYTES   # counter bytes per true byte
+        factor = (max(ref) * 1024) / COPY_BYTES   # counter bytes per true byte
         out[name] = {"kib_per_launch_raw": sum(kern) / len(kern), "launches": len(kern),
-                     "copy_kib_raw": max(copy), "copy_factor": factor,
+                     "yardstick": ref_name, "yardstick_kib_raw": max(ref),
+                     "factor": factor,
                      "bytes_per_launch": sum(kern) / len(kern) * 1024 / factor}
     out["hbm_bytes_per_launch"] = out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"]
     out["kernel_source_sha256"] = product_kernel_hash()
@@ -497,8 +515,8 @@ def main() -> int:
         "other_workloads": extra,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": (f"k_gemm16<{prec.name}>" if gcp.MFMA_DTYPE[prec] in ("fp16", "bf16")
-                                else f"k_gemm<{prec.name}>"),
+                     "kernel": (("k_gemm16" if gcp.MFMA_DTYPE[prec] in ("fp16", "bf16") else "k_gemm")
+                                + f"<{prec.name}>"),
                      "algorithmic_flops_per_launch": flops_product,
                      "launches_per_solve": launches,
                      "ms_per_launch": gemm_ms_avg,

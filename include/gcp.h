@@ -275,6 +275,15 @@ int gcp_purify_static(const double *H, int64_t ldh, int64_t M, int64_t N, double
                       double emax, const gcp_options *opt, void *D, int32_t dtype, int64_t ldd,
                       void *stream, gcp_result *out);
 
+/* Measurement support (not part of the method): reads `bytes` bytes of the
+ * device buffer buf (a multiple of 65536) with the same loads the 16-bit
+ * product kernel uses for its panels (global memory straight to LDS, 16 bytes
+ * per lane, 128-byte row segments) and writes nothing, on the given stream.
+ * A memory-traffic counter read over this kernel gives the factor that turns
+ * that counter into bytes for the product kernel's loads.  Returns OK,
+ * INVALID_ARG (NULL buf, bytes not a positive multiple of 65536) or HIP. */
+int gcp_stream_lds(const void *buf, int64_t bytes, void *stream);
+
 /* Per-iterate history of the last gcp_purify: GCP_HIST_COLS doubles per row,
  *   [n, Tr D, Tr D^2, Tr D^3, c_n, Omega = ||D^2-D||_F^2, gamma_n = (1-2c_n)/3,
  *    L_n = Omega - gamma_n (3 Tr D^2 - 2 Tr D^3 - N) (eq. mcw4b), ||D_{n+1} - D_n||_F]

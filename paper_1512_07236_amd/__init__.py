@@ -139,6 +139,8 @@ def load_library() -> ctypes.CDLL:
     L.gcp_purify_static.argtypes = [vp, i64, i64, i64, dbl, dbl, ctypes.POINTER(Options), vp, i32,
                                     i64, vp, ctypes.POINTER(CResult)]
     L.gcp_purify_static.restype = ctypes.c_int
+    L.gcp_stream_lds.argtypes = [vp, i64, vp]
+    L.gcp_stream_lds.restype = ctypes.c_int
     _lib = L
     return L
 

@@ -1218,6 +1218,19 @@ extern "C" int gcp_get_history(const gcp_ctx *c, double *rows, int32_t max_rows,
   return GCP_OK;
 }
 
+extern "C" int gcp_stream_lds(const void *buf, int64_t bytes, void *stream) {
+  if (!buf || bytes <= 0 || bytes % 65536 != 0 || bytes / 65536 > 0x7fffffff) {
+    g_create_error = "gcp_stream_lds: need buf != NULL and bytes a positive multiple of 65536";
+    return GCP_ERR_INVALID_ARG;
+  }
+  const hipError_t e = launch_stream_lds(buf, bytes, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    g_create_error.set("gcp_stream_lds", hipGetErrorString(e));
+    return GCP_ERR_HIP;
+  }
+  return GCP_OK;
+}
+
 // ------------------------------------------------ solve without allocation
 // Workspace of gcp_purify_static: one copy per GPU, held until the process
 // ends.  In host code `scratch` names a host-side stand-in; its device

@@ -151,6 +151,8 @@ hipError_t launch_output(int prec, const OutArgs &a, hipStream_t st);
 hipError_t launch_convert(int pa, int pb, const void *in, const double *diag, void *out,
                           double *resid, int64_t Mp, hipStream_t st);
 hipError_t launch_reduce(const RedArgs &a, hipStream_t st);
+// Streams `bytes` (a multiple of 64 KiB) of buf into LDS with global_load_lds.
+hipError_t launch_stream_lds(const void *buf, int64_t bytes, hipStream_t st);
 // n 32-bit words of p set to zero by a kernel (no memset node in a captured graph)
 hipError_t launch_zero(void *p, int64_t nwords, hipStream_t st);
 hipError_t launch_hstats(const double *H, int64_t ldh, int64_t M, double *lo, double *hi,

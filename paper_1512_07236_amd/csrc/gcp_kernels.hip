@@ -209,7 +209,7 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
   if (tid == 0) g.tpart[lin] = ((tp[0] + tp[1]) + tp[2]) + tp[3];
 }
 
-// ------------------------------------------------ 16-bit products, three planes
+// ------------------------------------------------ 16-bit product kernel
 // Pairs of horizontally adjacent 128 x 128 tiles, (ti, 2c) and (ti, 2c+1),
 // share one row panel of the left operand: a 128 x 256 output per block of
 // 8 waves (2 per SIMD), each wave 64 rows x 64 columns of one tile (4 x 4
@@ -248,14 +248,13 @@ __device__ __forceinline__ void pair_of_block(int b, int nt, int &ti, int &cp, i
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-constexpr int NW3P = 8;              // waves per block of the eight-wave kernel (2 per SIMD)
-constexpr int NTH3P = 64 * NW3P;
+constexpr int NW16 = 8;              // waves per block of the 16-bit kernel (2 per SIMD)
+constexpr int NTH16 = 64 * NW16;
 
 // Eight waves of 64 x 64 with 16x16x32 products (any plane count; the
 // three-plane BF16X6 uses 64-byte plane segments per stage).
 template <int P>
-__global__ __launch_bounds__(NTH3P, 1) void k_gemm16_w8(GemmArgs g) {
-  constexpr int NW16 = NW3P, NTH16 = NTH3P;
+__global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
   using E = Enc<P>;
   using T = uint16_t;
   constexpr int NP = E::NP, KIND = E::KIND;
@@ -758,481 +757,6 @@ __global__ __launch_bounds__(NTH3P, 1) void k_gemm16_w8(GemmArgs g) {
   }
 }
 
-// ------------------------------------------------ 16-bit product kernel
-// One- and two-plane encodings.  One block per pair of horizontally
-// adjacent 128 x 128 tiles (ti, 2cp), (ti, 2cp+1) of the upper triangle:
-// 128 x 256 outputs, 4 waves, one per SIMD.  Wave w computes the 128 rows and
-// pair columns 64w .. 64w+63 as 4 x 2 blocks of 32 x 32 with
-// v_mfma_f32_32x32x16, which a single wave issues at the full rate of its
-// SIMD's matrix core; its chunk accumulators and running totals (256 FP32
-// values per lane) live in the accumulation registers.
-//
-// A K stage is one 128-byte segment of every panel row: 32 K values of both
-// planes (two-plane storage interleaves them in 32-column blocks) or 64 K
-// values of one plane.  The segment holds four 16-value K slots; a product
-// pairs one slot of A with one of B:
-//   two planes: half h of the stage = slots (hi h, lo h), products
-//               hi*hi, hi*lo, lo*hi (the lo*lo term is below the encoding's
-//               rounding);
-//   one plane:  half h = slots (2h, 2h + 1), one product each.
-// The panels stream from HBM straight into a 3-stage LDS ring
-// (global_load_lds, 16 bytes per lane, 8 rows per wave instruction).
-// Fragments are double-buffered by K half, and the stage barrier sits
-// between the two halves: the products of half 0 of stage k are issued
-// while half 1's fragments are read; after the barrier of stage k + 1 the
-// products of half 1 of stage k run while half 0 of stage k + 1 is read and
-// the loads of stage k + 3 are issued into the buffer stage k has freed.
-//
-// All products of a stage go into a chunk accumulator, added into the
-// running total every `fold` stages: with r products per stage and n = K/32
-// stages the accumulated rounding grows like sqrt(r fold + n / fold), not
-// sqrt(r n); fold = sqrt(n / r) (the default) minimises it.
-constexpr int NW16 = 4;               // waves per block (one per SIMD)
-constexpr int NTH16 = 64 * NW16;
-
-template <int P>
-__global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
-  using E = Enc<P>;
-  using T = uint16_t;
-  constexpr int NP = E::NP, KIND = E::KIND;
-  static_assert(NP <= 2, "three-plane encodings use k_gemm16_w8");
-  constexpr int AR = TILE, BR = PAIR_COLS * TILE;   // panel rows
-  constexpr int RH = 64;                            // halves per panel row per stage
-  constexpr int STAGE = (AR + BR) * RH;             // 48 KB
-  constexpr int NBUF = 3, PD = NBUF - 1;            // ring, prefetch distance (stages)
-  constexpr int LPS = (AR + BR) / 8 / NW16;         // loads per wave per stage (12)
-  static_assert((AR + BR) / 8 % NW16 == 0, "whole load blocks per wave");
-  // s_waitcnt immediates: vmcnt <= LPS (one later stage may still fly), or
-  // 0; lgkmcnt 0 in both (this wave's fragment reads are complete); expcnt
-  // not waited on
-  constexpr int WAIT_ONE = (LPS & 0xF) | ((LPS >> 4) << 14) | (0x7 << 4);
-  constexpr int WAIT_ALL = (0x7 << 4);
-  constexpr int EPLD = TILE + 4;                    // epilogue row pitch (floats)
-  constexpr int WPT = NW16;                         // waves per tile in the epilogue
-  constexpr int EVEC = 5 * TILE + BR;               // FP64 side vectors staged for the epilogue
-  constexpr int EPI =
-      (2 * TILE * EPLD * 4 + (2 + 2 * WPT) * TILE * 8 + 2 * WPT * 8 + EVEC * 8) / 2;   // halves
-  constexpr int SMEM = NBUF * STAGE > EPI ? NBUF * STAGE : EPI;
-  __shared__ __attribute__((aligned(16))) T smem[SMEM];
-  if (g.status && *g.status != 0) return;   // the solve has stopped
-
-  // whole pair, or split s of a tail pair over K stages [kbase, kbase + nk)
-  const int nk_all = (int)(g.Mp * NP / 64);
-  int lin, split = -1, kbase = 0, nk = nk_all;
-  if ((int)blockIdx.x < g.nfull) {
-    lin = xcd_run((int)blockIdx.x, g.nfull);
-  } else {
-    const int u = (int)blockIdx.x - g.nfull;
-    split = u % g.nsplit;
-    lin = g.nfull + u / g.nsplit;
-    kbase = split * nk_all / g.nsplit;
-    nk = (split + 1) * nk_all / g.nsplit - kbase;
-  }
-  int ti, cpair;
-  pair_of_index(lin, g.nt, ti, cpair);
-  const int64_t Mp = g.Mp;
-  const int64_t arow0 = (int64_t)ti * TILE, brow0 = (int64_t)cpair * BR;
-  const T *__restrict__ Ag = (const T *)g.A;
-  const T *__restrict__ Bg = (const T *)g.B;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int l32 = lane & 31;
-  const int h = wave >> 1;                 // tile of the pair this wave computes
-  const int tcol0 = (wave & 1) * 64;       // its first column inside that tile
-  const bool valid = cpair * PAIR_COLS + h >= ti;
-
-  // Chunk c of stage row R sits at slot c ^ ((R / 2) % 8): a fragment read
-  // (32 consecutive rows, two chunks) then touches every slot equally.
-  auto swz = [](int R) { return (R >> 1) & 7; };
-  auto issue = [&](int kt, int buf) {
-    T *st = smem + buf * STAGE;
-#pragma unroll
-    for (int q = 0; q < LPS; ++q) {
-      const int blk = wave + NW16 * q;
-      const int R = blk * 8 + (lane >> 3);
-      const int c = (lane & 7) ^ swz(R);
-      const T *src = (R < AR ? Ag + (arow0 + R) * (NP * Mp) : Bg + (brow0 + R - AR) * (NP * Mp)) +
-                     (int64_t)(kbase + kt) * RH + c * 8;
-      __builtin_amdgcn_global_load_lds((const void *)src, (lds_void *)(st + blk * 8 * RH), 16, 0, 0);
-    }
-  };
-  // K slot of fragment x (0, 1) in half hf of a stage
-  auto kslot = [](int x, int hf) { return NP == 2 ? 2 * x + hf : 2 * hf + x; };
-  auto frag = [&](const T *st, int R, int ks) -> v4u {
-    return *(const v4u *)(st + R * RH + ((2 * ks + (lane >> 5)) ^ swz(R)) * 8);
-  };
-  v4u a0[4][2], b0[2][2], a1[4][2], b1[2][2];
-  auto read_half = [&](int kt, int hf, v4u (&a)[4][2], v4u (&b)[2][2]) {
-    const T *st = smem + (kt % NBUF) * STAGE;
-#pragma unroll
-    for (int x = 0; x < 2; ++x) {
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) b[bj][x] = frag(st, AR + wave * 64 + bj * 32 + l32, kslot(x, hf));
-#pragma unroll
-      for (int bi = 0; bi < 4; ++bi) a[bi][x] = frag(st, bi * 32 + l32, kslot(x, hf));
-    }
-  };
-  v16f acc[4][2], tot[4][2];
-#pragma unroll
-  for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      acc[bi][bj] = v16f{};
-      tot[bi][bj] = v16f{};
-    }
-  // products of a half: (slot of A, slot of B), largest first
-  constexpr int NPR = NP == 2 ? 3 : 2;
-  constexpr int XA[3] = {0, 0, 1};
-  constexpr int XB[3] = {0, 1, 0};
-  constexpr int YA[2] = {0, 1};
-  auto mma_half = [&](const v4u (&a)[4][2], const v4u (&b)[2][2]) {
-#pragma unroll
-    for (int pr = 0; pr < NPR; ++pr)
-#pragma unroll
-      for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-          const int xa = NP == 2 ? XA[pr] : YA[pr], xb = NP == 2 ? XB[pr] : YA[pr];
-          acc[bi][bj] = mfma32<KIND>(a[bi][xa], b[bj][xb], acc[bi][bj]);
-        }
-  };
-  const int fold = g.fold;   // >= 1 (resolved on the host)
-  auto fold_if_due = [&](int kt) {
-    if ((kt + 1) % fold == 0 || kt == nk - 1) {
-#pragma unroll
-      for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-          tot[bi][bj] += acc[bi][bj];
-          acc[bi][bj] = v16f{};
-        }
-    }
-  };
-  // Bare s_barrier: __syncthreads() would add a workgroup release fence,
-  // which waits for every outstanding LDS-DMA load and so drains the
-  // pipeline.  The empty asm statements keep the compiler from moving LDS
-  // accesses across it, the scheduling barriers keep the matrix products on
-  // their side of it; the waits before it provide the hardware ordering.
-  auto barrier = [] {
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_sched_barrier(0);
-    asm volatile("" ::: "memory");
-  };
-  // this wave's loads of stage kt have landed (the next stage's may still
-  // fly) and its fragment reads are complete; then everyone's
-  auto enter_stage = [&](int kt) {
-    if (kt + 1 < nk)
-      __builtin_amdgcn_s_waitcnt(WAIT_ONE);
-    else
-      __builtin_amdgcn_s_waitcnt(WAIT_ALL);
-    barrier();
-  };
-  // Waves of a tile below the diagonal run the same instruction stream (their
-  // results are discarded).
-#pragma unroll
-  for (int s0 = 0; s0 < PD; ++s0)
-    if (s0 < nk) issue(s0, s0);
-  enter_stage(0);
-  if (PD < nk) issue(PD, PD % NBUF);
-  read_half(0, 0, a0, b0);
-  for (int kt = 0; kt < nk; ++kt) {
-    read_half(kt, 1, a1, b1);
-    mma_half(a0, b0);
-    if (kt + 1 < nk) {
-      enter_stage(kt + 1);   // stage kt + 1 has landed; stage kt's buffer is free
-      if (kt + 1 + PD < nk) issue(kt + 1 + PD, (kt + 1 + PD) % NBUF);
-      read_half(kt + 1, 0, a0, b0);
-    }
-    mma_half(a1, b1);
-    fold_if_due(kt);
-  }
-  __syncthreads();   // all waves done with the stage buffers (reused below)
-
-  if (split >= 0) {
-    // K-split tail pair: publish this split's FP32 totals; the last split to
-    // arrive adds all of them in split order (so the sum does not depend on
-    // the arrival order) and runs the epilogue.
-    constexpr int NV = 4 * 2 * 4;   // float4 per thread
-    const int q = (int)blockIdx.x - g.nfull;
-    const int pair = q / g.nsplit;
-    float4 *wsp = (float4 *)g.ws + (int64_t)q * NV * NTH16;
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-          const v16f t = tot[bi][bj];
-          wsp[((bi * 2 + bj) * 4 + r4) * NTH16 + tid] =
-              make_float4(t[4 * r4], t[4 * r4 + 1], t[4 * r4 + 2], t[4 * r4 + 3]);
-        }
-    __threadfence();
-    // The arrival flag lives in the (now idle) stage buffers: a second
-    // __shared__ object would make the compiler wait for every LDS-DMA load
-    // before each LDS read of the main loop (it cannot tell them apart).
-    unsigned *last = (unsigned *)smem;
-    __syncthreads();
-    if (tid == 0) *last = (atomicAdd(g.cnt + pair, 1u) == (unsigned)g.nsplit - 1);
-    __syncthreads();
-    if (!*last) return;
-    __syncthreads();   // flag read by all before the epilogue reuses smem
-    __threadfence();
-    const float4 *w0 = (const float4 *)g.ws + (int64_t)pair * g.nsplit * NV * NTH16;
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int r4 = 0; r4 < 4; ++r4) {
-          double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-          for (int s = 0; s < g.nsplit; ++s) {
-            const float4 v = w0[((int64_t)s * NV + (bi * 2 + bj) * 4 + r4) * NTH16 + tid];
-            s0 += v.x;
-            s1 += v.y;
-            s2 += v.z;
-            s3 += v.w;
-          }
-          tot[bi][bj][4 * r4] = (float)s0;
-          tot[bi][bj][4 * r4 + 1] = (float)s1;
-          tot[bi][bj][4 * r4 + 2] = (float)s2;
-          tot[bi][bj][4 * r4 + 3] = (float)s3;
-        }
-    if (tid == 0) g.cnt[pair] = 0u;   // ready for the next launch
-  }
-
-  // ------------------------------------------------------------ epilogue
-  // Phase 0: every wave dumps its FP32 results into LDS, V[tile][row][col]
-  // with a row pitch of 132 floats.
-  float *V = (float *)smem;
-  double *rp = (double *)(V + 2 * TILE * EPLD);   // [2 tiles][128] row sums
-  double *cpart = rp + 2 * TILE;                  // [2 tiles][WPT waves][128] column sums
-  double *tp = cpart + 2 * WPT * TILE;            // [2 tiles][WPT waves] tile sums
-  // The FP64 side vectors of the block's rows (rD, s2, dg, d2, d3) and
-  // columns (rD) are staged in LDS: read per element from global memory they
-  // would each wait for the stores before them (the compiler cannot tell
-  // them from the output), one memory round trip per element.
-  double *vrow = tp + 2 * WPT;                    // [5][128]
-  double *vcol = vrow + 5 * TILE;                 // [256]
-  for (int q = tid; q < EVEC; q += NTH16) {
-    if (q < 5 * TILE) {
-      const int k = q / TILE;
-      const int64_t i = arow0 + q % TILE;
-      double v = 0.0;
-      if (k == 0) v = g.rD[i];
-      else if (k == 1) v = g.mode == 1 ? g.s2[i] : 0.0;
-      else if (k == 2) v = g.dg[i];
-      else if (k == 3) v = g.d2[i];
-      else v = g.mode == 1 ? g.d3[i] : 0.0;
-      vrow[q] = v;
-    } else {
-      vcol[q - 5 * TILE] = g.rD[brow0 + q - 5 * TILE];
-    }
-  }
-  if (valid) {
-#pragma unroll
-    for (int bi = 0; bi < 4; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-          V[(h * TILE + bi * 32 + acc32_row(lane, r)) * EPLD + tcol0 + bj * 32 + l32] = tot[bi][bj][r];
-  }
-  __syncthreads();
-  // Phase 1, one tile of the pair at a time: 256 threads, each owning one
-  // 8 x 8 block (block row br, block column bc).  Row-contiguous 16-byte
-  // loads of D (and X2) and stores of the result; the mirrored store writes
-  // the transposed block, again as 16-byte rows.
-  const int br = tid >> 4, bc = tid & 15, wt = tid >> 6;
-  const int64_t i0 = arow0 + br * 8;
-  const double S = E::PROD_SCALE;
-  T *__restrict__ Og = (T *)g.out;
-  double a_coef = 0.0, b_coef = 0.0, e_coef = 0.0;
-  if (g.mode == 1) update_coefs(g.method, g.coef[0], a_coef, b_coef, e_coef);
-#pragma unroll 1
-  for (int th = 0; th < PAIR_COLS; ++th) {
-    const int tjj = cpair * PAIR_COLS + th;
-    const bool tvalid = tjj >= ti, dtile = tjj == ti;
-    double rsum[8], csum[8], tsum = 0.0;
-#pragma unroll
-    for (int r = 0; r < 8; ++r) rsum[r] = csum[r] = 0.0;
-    if (tvalid && !(dtile && br > bc)) {   // blocks below the diagonal are mirrors
-      const bool dblk = dtile && br == bc;
-      const int64_t j0 = (int64_t)tjj * TILE + bc * 8;
-      // Encoded results, row r of the block, 8 halves per plane, parked in
-      // this thread's own 8 x 8 block of V (32 bytes per row, already
-      // consumed when row r is encoded) for the mirrored store.
-      uint32_t *park = (uint32_t *)(V + (th * TILE + br * 8) * EPLD + bc * 8);   // row r at park + r * EPLD
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const int64_t i = i0 + r;
-        v4u dv[NP], xv[NP];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          dv[p] = *(const v4u *)(Bg + eoff<P>(i, j0, p, Mp));
-          if (g.mode == 1) xv[p] = *(const v4u *)(Ag + eoff<P>(i, j0, p, Mp));
-        }
-        const float *vr = V + (th * TILE + br * 8 + r) * EPLD + bc * 8;
-        uint16_t o[NP][8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int64_t j = j0 + e;
-          T dp[NP], op[NP];
-#pragma unroll
-          for (int p = 0; p < NP; ++p) dp[p] = (uint16_t)(dv[p][e >> 1] >> (16 * (e & 1)));
-          const double v = (double)vr[e] * S;
-          double prod, diff;
-          if (g.mode == 0) {
-            double Dm, x2;
-            if (i == j) {
-              Dm = vrow[2 * TILE + br * 8 + r];
-              x2 = vrow[3 * TILE + br * 8 + r];
-            } else {
-              Dm = E::dec(dp);
-              x2 = v + Dm * (vrow[br * 8 + r] + vcol[th * TILE + bc * 8 + e]);
-            }
-            E::enc(x2, op);
-            const double x2m = (i == j) ? x2 : E::dec(op);
-            if (i == j) g.s2[i] = x2 - E::dec(op);
-            prod = x2m * Dm;
-            diff = x2m - Dm;
-          } else {
-            double Dm, dn;
-            if (i == j) {
-              Dm = vrow[2 * TILE + br * 8 + r];
-              dn = a_coef * Dm + b_coef * vrow[3 * TILE + br * 8 + r] + e_coef * vrow[4 * TILE + br * 8 + r];
-            } else {
-              T xp[NP];
-#pragma unroll
-              for (int p = 0; p < NP; ++p) xp[p] = (uint16_t)(xv[p][e >> 1] >> (16 * (e & 1)));
-              Dm = E::dec(dp);
-              const double X2m = E::dec(xp);
-              const double x3 = v + X2m * vcol[th * TILE + bc * 8 + e] + vrow[TILE + br * 8 + r] * Dm;
-              dn = a_coef * Dm + b_coef * X2m + e_coef * x3;
-            }
-            E::enc(dn, op);
-            const double dnm = (i == j) ? dn : E::dec(op);
-            if (i == j) {
-              g.dg_new[i] = dn;
-              g.rD_new[i] = dn - E::dec(op);
-            }
-            prod = dnm * dnm;
-            diff = dnm - Dm;
-          }
-#pragma unroll
-          for (int p = 0; p < NP; ++p) o[p][e] = op[p];
-          if (dblk && i > j) continue;   // lower half of a diagonal block
-          rsum[r] += prod;
-          if (i != j) {
-            csum[e] += prod;
-            tsum += 2.0 * diff * diff;
-          } else {
-            tsum += diff * diff;
-          }
-        }
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          v4u w;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) w[q] = (uint32_t)o[p][2 * q] | ((uint32_t)o[p][2 * q + 1] << 16);
-          *(v4u *)(park + r * EPLD + 4 * p) = w;
-          if (!dblk) {
-            *(v4u *)(Og + eoff<P>(i, j0, p, Mp)) = w;
-          } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-              if (e >= r) Og[eoff<P>(i, j0 + e, p, Mp)] = o[p][e];
-          }
-        }
-      }
-      // mirrored (transposed) block: row j0+e gets column e of the block
-#pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        v4u obp[8];
-#pragma unroll
-        for (int r = 0; r < 8; ++r) obp[r] = *(const v4u *)(park + r * EPLD + 4 * p);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          if (!dblk) {
-            v4u w;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const uint32_t lo = (obp[2 * q][e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-              const uint32_t hi = (obp[2 * q + 1][e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-              w[q] = lo | (hi << 16);
-            }
-            *(v4u *)(Og + eoff<P>(j0 + e, i0, p, Mp)) = w;
-          } else {
-#pragma unroll
-            for (int r = 0; r < 8; ++r)
-              if (r < e)
-                Og[eoff<P>(j0 + e, i0 + r, p, Mp)] =
-                    (uint16_t)((obp[r][e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-          }
-        }
-      }
-    }
-    // row sums: the 16 threads of a block row (lanes differing in bits 0..3)
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      double v = rsum[r];
-      v += shfl_xor_d(v, 1);
-      v += shfl_xor_d(v, 2);
-      v += shfl_xor_d(v, 4);
-      v += shfl_xor_d(v, 8);
-      rsum[r] = v;
-    }
-    // column sums: the 4 block rows of a wave (bits 4..5), then the tile's waves
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      double v = csum[e];
-      v += shfl_xor_d(v, 16);
-      v += shfl_xor_d(v, 32);
-      csum[e] = v;
-    }
-    tsum += shfl_xor_d(tsum, 1);
-    tsum += shfl_xor_d(tsum, 2);
-    tsum += shfl_xor_d(tsum, 4);
-    tsum += shfl_xor_d(tsum, 8);
-    tsum += shfl_xor_d(tsum, 16);
-    tsum += shfl_xor_d(tsum, 32);
-    if ((tid & 15) == 0) {
-#pragma unroll
-      for (int r = 0; r < 8; ++r) rp[th * TILE + br * 8 + r] = rsum[r];
-    }
-    if ((lane >> 4) == 0) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) cpart[(th * WPT + wt) * TILE + bc * 8 + e] = csum[e];
-    }
-    if (lane == 0) tp[th * WPT + wt] = tsum;
-  }
-  __syncthreads();
-  // partial sums of both tiles: 128 threads per tile
-  {
-    const int th = tid >> 7, x = tid & 127;
-    const int tjj = cpair * PAIR_COLS + th;
-    const bool tvalid = tjj >= ti, dtile = tjj == ti;
-    if (tvalid) {
-      const double rs = rp[th * TILE + x];
-      double cs = 0.0;
-#pragma unroll
-      for (int w = 0; w < WPT; ++w) cs += cpart[(th * WPT + w) * TILE + x];
-      if (!dtile) {
-        g.part[(int64_t)tjj * Mp + arow0 + x] = rs;
-        g.part[(int64_t)ti * Mp + (int64_t)tjj * TILE + x] = cs;
-      } else {
-        g.part[(int64_t)ti * Mp + arow0 + x] = rs + cs;
-      }
-    }
-  }
-  if (tid < 2) {   // 0 for a skipped tile
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < WPT; ++w) t += tp[tid * WPT + w];
-    g.tpart[2 * lin + tid] = t;
-  }
-}
-
 int pair_count(int nt) {
   int n = 0;
   for (int t = 0; t < nt; ++t) n += nt / PAIR_COLS - t / PAIR_COLS;
@@ -1636,18 +1160,10 @@ hipError_t launch_convert(int pa, int pb, const void *in, const double *diag, vo
 }
 
 // ---------------------------------------------------------------- dispatch
-// One- and two-plane encodings: the one-wave-per-SIMD kernel (k_gemm16) once
-// it is faster than the eight-wave one; both are checked element-wise.
-constexpr bool kOneWavePerSimd = false;
 template <int P>
 static hipError_t launch_gemm_p(const GemmArgs &g, int ntiles, hipStream_t st) {
   if constexpr (Enc<P>::KIND >= 2)
-  {
-    if constexpr (Enc<P>::NP == 3 || !kOneWavePerSimd)
-      k_gemm16_w8<P><<<gemm16_blocks(g), NTH3P, 0, st>>>(g);
-    else
-      k_gemm16<P><<<gemm16_blocks(g), NTH16, 0, st>>>(g);
-  }
+    k_gemm16<P><<<gemm16_blocks(g), NTH16, 0, st>>>(g);
   else
     k_gemm<P><<<ntiles, NTH, 0, st>>>(g);
   return hipGetLastError();
@@ -1723,6 +1239,25 @@ hipError_t launch_zero(void *p, int64_t nwords, hipStream_t st) {
   int64_t nb = (nwords + 255) / 256;
   if (nb > 1024) nb = 1024;
   k_zero<<<(unsigned)nb, 256, 0, st>>>((uint32_t *)p, nwords);
+  return hipGetLastError();
+}
+
+// Traffic yardstick: 64 KiB per block, each wave loading 16 KiB as sixteen
+// contiguous wave instructions of 1 KiB (16 bytes per lane) straight into
+// LDS, the load type of the 16-bit product kernel's panels.
+__global__ __launch_bounds__(256) void k_stream_lds(const uint16_t *buf) {
+  __shared__ __attribute__((aligned(16))) uint16_t lds[32768];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint16_t *src = buf + (int64_t)blockIdx.x * 32768 + wave * 8192 + lane * 8;
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    __builtin_amdgcn_global_load_lds((const void *)(src + q * 512),
+                                     (lds_void *)(lds + wave * 8192 + q * 512), 16, 0, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
+hipError_t launch_stream_lds(const void *buf, int64_t bytes, hipStream_t st) {
+  k_stream_lds<<<(unsigned)(bytes / 65536), 256, 0, st>>>((const uint16_t *)buf);
   return hipGetLastError();
 }
 

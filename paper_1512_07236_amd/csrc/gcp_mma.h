@@ -18,7 +18,6 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef __bf16 v8b __attribute__((ext_vector_type(8)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int TILE = 128;   // output tile edge
 constexpr int NTH = 256;    // threads per tile: 4 waves in a 2 x 2 grid of 64 x 64
@@ -49,23 +48,6 @@ __device__ __forceinline__ v4f mfma16(v4u a, v4u b, v4f c) {
   else
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a),
                                                   __builtin_bit_cast(v8h, b), c, 0, 0, 0);
-}
-
-// 32x32 output block per MFMA over K = 16: lane l supplies row (or column)
-// l % 32 of its operand at K offsets 8 (l / 32) .. + 7 (the same for A and
-// B) and holds column l % 32 of the result at rows 8 (r / 4) + 4 (l / 32) +
-// r % 4, r = 0..15.
-template <int KIND>
-__device__ __forceinline__ v16f mfma32(v4u a, v4u b, v16f c) {
-  if constexpr (KIND == 2)
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8b, a),
-                                                   __builtin_bit_cast(v8b, b), c, 0, 0, 0);
-  else
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a),
-                                                  __builtin_bit_cast(v8h, b), c, 0, 0, 0);
-}
-__device__ __forceinline__ int acc32_row(int lane, int r) {
-  return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
 }
 
 __device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
@@ -100,47 +82,6 @@ __device__ __forceinline__ void tile_of_block(int b, int nt, int &ti, int &tj, i
     }
   }
   ti = tj = 0;   // not reached for b < ntiles
-}
-
-// Tile pairs (ti, cp): row tile ti and the two column tiles 2cp, 2cp + 1 of
-// the upper triangle (ti <= 2 cp + 1).  Order: groups of CG column pairs;
-// inside a group rows ascend and the group's column pairs ascend in a row,
-// so 32 consecutive pairs cover about 8 row tiles x 4 column pairs.  Blocks
-// take this order in one contiguous run per XCD (xcd_run): the blocks that
-// an XCD runs at one time then share 8 row panels and 4 column-pair panels
-// in its L2.
-constexpr int PAIR_GROUP = 4;
-
-__host__ __device__ inline int xcd_run(int b, int total) {
-  const int xcd = b & 7, loc = b >> 3, q = total >> 3, r = total & 7;
-  return xcd * q + (xcd < r ? xcd : r) + loc;
-}
-
-__host__ __device__ inline void pair_of_index(int L, int nt, int &ti, int &cp) {
-  const int npc = nt / 2;
-  for (int c0 = 0; c0 < npc; c0 += PAIR_GROUP) {
-    const int w = npc - c0 < PAIR_GROUP ? npc - c0 : PAIR_GROUP;
-    const int frows = 2 * c0 + 2;            // rows where every pair of the group is valid
-    const int nf = frows * w;
-    if (L < nf) {
-      ti = L / w;
-      cp = c0 + L % w;
-      return;
-    }
-    L -= nf;
-    const int rend = 2 * (c0 + w) < nt ? 2 * (c0 + w) : nt;
-    for (int r = frows; r < rend; ++r) {       // the diagonal band: cp >= r / 2
-      const int first = r / 2 > c0 ? r / 2 : c0;
-      const int cnt = c0 + w - first;
-      if (L < cnt) {
-        ti = r;
-        cp = first + L;
-        return;
-      }
-      L -= cnt;
-    }
-  }
-  ti = cp = 0;   // not reached for L < the number of pairs
 }
 
 // LDS geometry of the FP64 / FP32 tile product: K stages of 128 bytes per

@@ -15,6 +15,7 @@ import bench  # noqa: E402
 
 KERNEL = "void gcp::k_gemm16<5>(gcp::GemmArgs)"
 COPY = "__amd_rocclr_copyBuffer"
+STREAM = "gcp::k_stream_lds(unsigned short const*)"
 
 
 def _write_counters(d, counter, rows):
@@ -42,20 +43,23 @@ def sandbox(tmp_path, monkeypatch):
     return tmp_path
 
 
-def test_pmc_summary_scales_each_counter_by_the_copy(sandbox):
+def test_pmc_summary_scales_each_counter_by_its_yardstick(sandbox):
     copy_kib = bench.COPY_BYTES / 1024
-    # FETCH_SIZE reads half of the copy's true bytes, WRITE_SIZE all of them
+    # FETCH_SIZE is scaled by the global-to-LDS stream of known size (here it
+    # reads half of its true bytes), WRITE_SIZE by the copy (all of them);
+    # launches that did no work (past a solve's stop) are left out
     _write_counters(sandbox / "fetch", "FETCH_SIZE",
-                    [(KERNEL, 3.0e6), (KERNEL, 3.2e6), (COPY, 0.5 * copy_kib), ("other", 9e9)])
+                    [(KERNEL, 3.0e6), (KERNEL, 3.2e6), (KERNEL, 0.0), (STREAM, 0.5 * copy_kib),
+                     (COPY, 0.7 * copy_kib), ("other", 9e9)])
     _write_counters(sandbox / "write", "WRITE_SIZE",
                     [(KERNEL, 4.0e5), (KERNEL, 6.0e5), (COPY, copy_kib)])
     assert bench.summarize_pmc("fp16x3", 1, str(sandbox / "fetch"), str(sandbox / "write")) == 0
     d = json.load(open(sandbox / "profiles" / "gemm_fp16x3_M8192_pmc.json"))
     assert d["kernel"] == "k_gemm16<5>" and d["kernel_source_sha256"] == "source-a"
     assert d["FETCH_SIZE"]["launches"] == 2
-    assert d["FETCH_SIZE"]["copy_factor"] == pytest.approx(0.5)
+    assert d["FETCH_SIZE"]["factor"] == pytest.approx(0.5)
     assert d["FETCH_SIZE"]["bytes_per_launch"] == pytest.approx(3.1e6 * 1024 / 0.5)
-    assert d["WRITE_SIZE"]["copy_factor"] == pytest.approx(1.0)
+    assert d["WRITE_SIZE"]["factor"] == pytest.approx(1.0)
     assert d["WRITE_SIZE"]["bytes_per_launch"] == pytest.approx(5.0e5 * 1024)
     assert d["hbm_bytes_per_launch"] == pytest.approx(3.1e6 * 1024 / 0.5 + 5.0e5 * 1024)
     # the summary is used while the kernel source is the profiled one, and only then
@@ -65,9 +69,9 @@ def test_pmc_summary_scales_each_counter_by_the_copy(sandbox):
     assert bench.pmc_traffic("gemm_bf16x6_M8192") is None
 
 
-def test_pmc_summary_needs_the_copy_reference(sandbox):
-    # without the calibration copy (or with one far smaller than 1 GiB) no
-    # scale factor exists: the summary fails instead of guessing
+def test_pmc_summary_needs_the_yardsticks(sandbox):
+    # without the calibration kernels no scale factor exists: the summary
+    # fails instead of guessing
     _write_counters(sandbox / "fetch", "FETCH_SIZE", [(KERNEL, 3.0e6), (COPY, 10.0)])
     _write_counters(sandbox / "write", "WRITE_SIZE", [(KERNEL, 4.0e5)])
     assert bench.summarize_pmc("fp16x3", 1, str(sandbox / "fetch"), str(sandbox / "write")) == 1
