@@ -86,11 +86,14 @@ typedef struct {
     int32_t max_iter;    /* maximum number of updates (default 100) */
     double tol_ddbar;    /* stop when |Tr(D Dbar)| <= tol_ddbar (default 1e-6, the paper's) */
     double tol_idem;     /* stop when ||D^2 - D||_F <= tol_idem (default 0 = off) */
-    int32_t fold_every;  /* 16-bit encodings: add the FP32 chunk accumulator into a
-                            second FP32 total every fold_every*32 columns of K.
-                            0 (default) = sqrt(K/32 / products), which minimises
-                            the accumulated rounding, the dominant error of the
-                            split encodings at large M; a value >= K/32 never folds. */
+    int32_t fold_every;  /* FP32 and 16-bit encodings: add the FP32 chunk accumulator
+                            into a second FP32 total every fold_every K stages (32
+                            values of K per stage; 16-bit one- and two-plane
+                            encodings: 64 halves of a row).  0 (default) = sqrt(stages /
+                            accumulations per stage), which minimises the accumulated
+                            rounding, the dominant error of the split encodings and
+                            of FP32 at large M; a value >= the stage count never
+                            folds.  FP64 keeps one accumulator. */
     int32_t profile;     /* 1: time every matrix-product launch with HIP events */
     int32_t keep_iterates; /* 1: gcp_purify keeps D_0 .. D_{p-1} for gcp_backward, one
                               M x M matrix of the adjoint's type per update (default 0) */

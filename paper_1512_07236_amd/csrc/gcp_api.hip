@@ -190,7 +190,8 @@ static void PrecCfgInit(gcp_ctx *c, int k) {
   const int nk = np <= 2 ? (int)(c->Mp * np / 64) : (int)(c->Mp / 32);
   const double per_stage = np == 1 ? 2.0 : (double)products(prec);
   int f = c->opt.fold_every;
-  if (f <= 0) f = (int)std::lround(std::sqrt((double)nk / per_stage));
+  if (f <= 0)
+    f = prec == GCP_FP32 ? fp32_fold(c->Mp) : (int)std::lround(std::sqrt((double)nk / per_stage));
   q.fold = f < 1 ? 1 : f;
   q.nfull = pair_count(c->nt);
   q.nsplit = 1;
@@ -483,7 +484,10 @@ static double rounding_floor(const gcp_ctx *c, int k) {
   }
   const double u_acc = std::ldexp(1.0, prec == GCP_FP64 ? -53 : -24);
   double kappa = (double)c->Mp + 1.0;   // one accumulator over K
-  if (elem_size(prec) == 2) {
+  if (prec == GCP_FP32) {                // chunks of fold stages of 32 K values
+    const double f = (double)c->pc[k].fold;
+    kappa = 32.0 * f + (double)(c->Mp / 32) / f;
+  } else if (elem_size(prec) == 2) {
     const int np = plane_count(prec);
     const double stages = np <= 2 ? (double)c->Mp * np / 64.0 : (double)c->Mp / 32.0;
     const double per_stage = np == 1 ? 2.0 : (double)products(prec);

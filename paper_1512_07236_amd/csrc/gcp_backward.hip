@@ -93,7 +93,7 @@ __global__ __launch_bounds__(NTH, 2) void k_bgemm(BwdArgs a) {
   }
 
   Acc acc[4][4];
-  mma_tile<P>(Al, Bl, arow0, brow0, Mp, Mp * Mp, smem, acc);
+  mma_tile<P>(Al, Bl, arow0, brow0, Mp, Mp * Mp, smem, 0, acc);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1, l16 = lane & 15, lg = lane >> 4;

@@ -7,6 +7,16 @@
 
 namespace gcp {
 
+// Default fold period of the FP32 tile product, in K stages of 32 values:
+// with 8 accumulating MFMA steps per stage and n stages, a chunk accumulator
+// added into a running total every f stages rounds each term about 8f + n/f
+// times; f = sqrt(n / 8) minimises that (one accumulator: 8n).
+__host__ __device__ inline int fp32_fold(int64_t Mp) {
+  const double f = sqrt((double)(Mp / 32) / 8.0);
+  const int r = (int)(f + 0.5);
+  return r < 1 ? 1 : r;
+}
+
 // Device-resident scalars of one solve (FP64 traces and the decision).
 struct Scalars {
   double t1, t2, t3, omega, c, step;

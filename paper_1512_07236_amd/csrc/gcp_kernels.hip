@@ -69,7 +69,7 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
   const int wm = wave >> 1, wn = wave & 1, l16 = lane & 15, lg = lane >> 4;
 
   Acc acc0[4][4];
-  mma_tile<P>(Ag, Bg, arow0, brow0, Mp, PS, smem, acc0);
+  mma_tile<P>(Ag, Bg, arow0, brow0, Mp, PS, smem, g.fold, acc0);
 
   // ------------------------------------------------------------ epilogue
   const double S = E::PROD_SCALE;

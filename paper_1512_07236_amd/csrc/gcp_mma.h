@@ -10,6 +10,7 @@
 #include <stdint.h>
 
 #include "gcp_encode.h"
+#include "gcp_kernels.h"
 
 namespace gcp {
 
@@ -97,14 +98,17 @@ template <int P> struct MmaCfg {
   static constexpr int SMEM = 2 * NP * TILE * LDR; // elements of LDS
 };
 
-// acc[bi][bj] += A[arow0 + wm*64 + bi*16 .. , :] * B[brow0 + wn*64 + bj*16 .., :]^T
+// acc[bi][bj] = A[arow0 + wm*64 + bi*16 .. , :] * B[brow0 + wn*64 + bj*16 .., :]^T
 // over the whole K = Mp.  Planes of a multi-plane operand are PS elements
-// apart (FP64 / FP32 storage has one).  Ends with a barrier: smem is free.
+// apart (FP64 / FP32 storage has one).  FP32 accumulates each run of `fold`
+// K stages in a chunk accumulator and adds it into a running total (fold <=
+// 0: fp32_fold(Mp)); FP64 keeps one accumulator.  Ends with a barrier: smem
+// is free.
 template <int P>
 __device__ __forceinline__ void mma_tile(const typename Enc<P>::T *__restrict__ Ag,
                                          const typename Enc<P>::T *__restrict__ Bg,
                                          int64_t arow0, int64_t brow0, int64_t Mp, int64_t PS,
-                                         typename Enc<P>::T *smem,
+                                         typename Enc<P>::T *smem, int fold,
                                          typename AccType<Enc<P>::KIND>::type (&acc)[4][4]) {
   using C = MmaCfg<P>;
   using T = typename C::T;
@@ -139,12 +143,15 @@ __device__ __forceinline__ void mma_tile(const typename Enc<P>::T *__restrict__ 
       }
   };
 
+  constexpr bool FOLD = Enc<P>::KIND == 1;
+  Acc tot[4][4];
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = Acc{};
+    for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = tot[bi][bj] = Acc{};
 
   const int nk = (int)(Mp / KT);
+  const int f = fold > 0 ? fold : fp32_fold(Mp);
   gload(0);
   swrite();
   __syncthreads();
@@ -162,11 +169,26 @@ __device__ __forceinline__ void mma_tile(const typename Enc<P>::T *__restrict__ 
         for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma(af, bf[bj], acc[bi][bj]);
       }
     }
+    if (FOLD && ((kt + 1) % f == 0 || kt == nk - 1)) {
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj) {
+          tot[bi][bj] += acc[bi][bj];
+          acc[bi][bj] = Acc{};
+        }
+    }
     __syncthreads();
     if (kt + 1 < nk) {
       swrite();
       __syncthreads();
     }
+  }
+  if constexpr (FOLD) {
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = tot[bi][bj];
   }
 }
 

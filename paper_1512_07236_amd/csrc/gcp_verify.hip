@@ -38,7 +38,7 @@ __global__ __launch_bounds__(NTH, 2) void k_vgemm(VerifyArgs a) {
   const T *__restrict__ D = a.D;
   const T *Al = MODE == 0 ? D : a.H;
   v4d acc[4][4];
-  mma_tile<GCP_FP64>(Al, D, arow0, brow0, Mp, Mp * Mp, smem, acc);
+  mma_tile<GCP_FP64>(Al, D, arow0, brow0, Mp, Mp * Mp, smem, 0, acc);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1, l16 = lane & 15, lg = lane >> 4;

@@ -20,7 +20,8 @@ Worst-case model (bounds "det"):
     split products), a chunk accumulator holds `fold` stages, and the chunk
     is added into a running total: kappa = terms*fold + ceil(stages/fold) + 2
     (the 2 covers the K-split partial sum rounded once to FP32);
-    FP32/FP64 products: one accumulator over K, kappa = K + 1;
+    FP32 products: the same with 32 K values per stage;
+    FP64 products: one accumulator over K, kappa = K + 1;
   * split encodings drop the small cross products (lo*lo; for three planes
     mid*lo, lo*mid, lo*lo): at most u_drop P_ij;
   * encoding an element x to its planes errs by at most u_enc |x| + a_enc
@@ -88,8 +89,14 @@ def accumulation_kappa(M: int, precision: str, fold_every: int = 0) -> int:
     accumulation scheme (worst case), for the launch configuration the
     library chooses at size M."""
     Mp = padded(M)
-    if precision in ("fp64", "fp32"):
+    if precision == "fp64":
         return Mp + 1
+    if precision == "fp32":
+        # stages of 32 K values, 8 MFMA steps each; default fold sqrt(stages / 8)
+        stages = Mp // 32
+        fold = fold_every if fold_every > 0 else max(1, int(math.sqrt(stages / 8) + 0.5))
+        fold = min(fold, stages)
+        return 32 * fold + math.ceil(stages / fold) + 2
     np_ = PLANES[precision]
     # K per stage: 64 values of one plane, or 32 values of every plane
     stages = Mp * np_ // 64 if np_ <= 2 else Mp // 32

@@ -145,7 +145,7 @@ def test_late_updates_near_convergence(precision):
         check_step(it[n], it[n + 1], hist[n], precision, label=f"{precision} late")
 
 
-@pytest.mark.parametrize("precision", ["fp16x3", "bf16x6"])
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x6", "fp32"])
 def test_fold_periods_element_wise(precision):
     """Fold periods 1 and 'never' change only the rounding, within the bound
     of their own accumulation scheme."""
