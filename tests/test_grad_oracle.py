@@ -140,3 +140,69 @@ def test_adjoint_hole_particle_guess_matches_finite_differences(oracle_lib, alph
         fd = grad.loss_fd(H, N, lo, hi, p, P, dH, h=1e-5, alpha=alpha)
         an = float(np.sum(g * dH))
         assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (alpha, fd, an)
+
+
+@pytest.mark.parametrize("M,N,p", [(16, 5, 4), (20, 14, 5), (18, 9, 6)])
+def test_pmcp_adjoint_matches_finite_differences(oracle_lib, M, N, p):
+    """The PMCP recursion, eqs. (pm1a)/(pm1b): both coefficient branches
+    (c <= 1/2 and c > 1/2) appear among the cases, and each enters through
+    its coefficients and their c-derivatives."""
+    H, lo, hi = _case(M, N, 61 + M + N)
+    P = W.sym_gaussian(M, 62)
+    _, cs, *_ = grad.forward_iterates(H, N, lo, hi, p, method="pmcp")
+    g = grad.adjoint(H, N, lo, hi, p, P, method="pmcp")
+    for t in range(3):
+        dH = W.sym_gaussian(M, 200 + t)
+        fd = grad.loss_fd(H, N, lo, hi, p, P, dH, h=1e-5, method="pmcp")
+        an = float(np.sum(g * dH))
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (t, fd, an, cs)
+
+
+def test_pmcp_cases_cover_both_branches(oracle_lib):
+    seen = set()
+    for M, N, p in ((16, 5, 4), (20, 14, 5), (18, 9, 6)):
+        H, lo, hi = _case(M, N, 61 + M + N)
+        _, cs, *_ = grad.forward_iterates(H, N, lo, hi, p, method="pmcp")
+        seen |= {bool(c > 0.5) for c in cs}
+    assert seen == {False, True}
+
+
+def test_pmcp_forward_iterates_match_oracle(oracle_lib):
+    H, lo, hi = _case(20, 14, 95)
+    Ds, cs, *_ = grad.forward_iterates(H, 14, lo, hi, 5, method="pmcp")
+    r = oracle.purify_ex(H, 14, lo, hi, method="pmcp", init="pmcp", tol_ddbar=0.0, max_iter=5)
+    assert r.iters == 5
+    np.testing.assert_allclose(Ds[-1], r.D, atol=1e-13, rtol=0)
+
+
+@pytest.mark.parametrize("M,N", [(20, 3), (20, 17), (24, 5)])
+def test_alpha_search_adjoint_matches_finite_differences(oracle_lib, M, N):
+    """The alpha search of eq. (hpcpguessalpha): the slope follows
+    ||mu I - H||_F, so the gradient gains a term along mu I - H.  Directions:
+    random, the identity (no change of S), and mu I - H itself (all of the
+    change of S)."""
+    H, lo, hi = _case(M, N, 71 + M + N)
+    P = W.sym_gaussian(M, 72)
+    *_, alpha, searched = grad.guess(H, N, lo, hi, init="search")
+    assert searched and 0.0 < alpha < 1.0
+    p = 4
+    for method in ("hpcp", "pmcp"):
+        g = grad.adjoint(H, N, lo, hi, p, P, method=method, init="search")
+        mu = np.trace(H) / M
+        for dH in (W.sym_gaussian(M, 73), np.eye(M), mu * np.eye(M) - H):
+            fd = grad.loss_fd(H, N, lo, hi, p, P, dH, h=1e-5, method=method, init="search")
+            an = float(np.sum(g * dH))
+            assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (method, fd, an)
+
+
+def test_alpha_search_term_is_needed(oracle_lib):
+    """Dropping the search term (treating the searched alpha as fixed) breaks
+    the finite-difference agreement along mu I - H."""
+    M, N, p = 20, 3, 4
+    H, lo, hi = _case(M, N, 71 + M + N)
+    P = W.sym_gaussian(M, 72)
+    *_, alpha, _ = grad.guess(H, N, lo, hi, init="search")
+    g_fixed = grad.adjoint(H, N, lo, hi, p, P, alpha=alpha)
+    dH = np.trace(H) / M * np.eye(M) - H
+    fd = grad.loss_fd(H, N, lo, hi, p, P, dH, h=1e-5, init="search")
+    assert abs(fd - float(np.sum(g_fixed * dH))) > 1e-4 * max(1.0, abs(fd))
