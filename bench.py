@@ -231,6 +231,37 @@ def time_solve(gcp, H, w, steps, warmup, **opts):
     return dt, results, Dh
 
 
+def time_adjoint(gcp, H, w, prec, tol, args):
+    """The FP32 adjoint (gcp_backward) of the solve for L = u^T D u: one
+    warm-up and args.bwd_steps timed calls on the same kept iterates."""
+    import torch
+    M, N = w.M, w.N
+    log(f"[bench] adjoint of the {prec.name} solve (FP32): {args.bwd_steps} timed")
+    ctx = gcp.Context(M, precision=prec, tol_ddbar=tol, max_iter=100,
+                      fold_every=args.fold_every, profile=True, keep_iterates=True,
+                      bwd_precision="fp32")
+    ctx.init(H, N, w.emin, w.emax)
+    ctx.purify()
+    u = torch.from_numpy(np.random.default_rng(33).standard_normal(M)).cuda()
+    G = torch.outer(u, u)
+    ctx.backward(G)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.bwd_steps):
+        _, rb = ctx.backward(G)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / args.bwd_steps
+    ctx.close()
+    del G
+    bwd = {"precision": "fp32", "updates": rb.iters, "ms": tb * 1e3,
+           "tflops": rb.gemm_flops / tb / 1e12,
+           "gemm_ms_per_launch": rb.gemm_ms / max(rb.gemm_launches, 1),
+           "gemm_frac_of_fp32_peak": rb.gemm_flops / (rb.gemm_ms * 1e-3) / 1e12
+           / PEAK_TFLOPS["fp32"]}
+    log(f"[bench] adjoint: {tb*1e3:.1f} ms, {bwd['tflops']:.1f} TFLOP/s")
+    return bwd
+
+
 def extra_configs(gcp, args):
     """The other standard workloads, each timed once after a warm-up: the 1D
     chain (FP64, with the host checking after every update and every 4), the
@@ -335,6 +366,9 @@ def main() -> int:
     ap.add_argument("--headline-only", action="store_true",
                     help="only the warm-up and timed solves of the headline workload (for a "
                          "kernel trace that covers exactly those launches)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the timed FP32 adjoints (--bwd-steps) of the headline solve (for "
+                         "a kernel trace of the adjoint)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (the reference kernel that scales "
                          "rocprofv3 FETCH_SIZE/WRITE_SIZE to bytes)")
@@ -360,6 +394,8 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
 
     log("[bench] generating workload (seeded)")
     w = workloads.config(3, scale=args.scale)
@@ -369,6 +405,9 @@ def main() -> int:
     mfma_dtype = gcp.MFMA_DTYPE[prec]
     tol = args.tol
 
+    if args.adjoint_only:
+        print(json.dumps(time_adjoint(gcp, H, w, prec, args.tol, args)), flush=True)
+        return 0
     log(f"[bench] {prec.name}: {args.warmup} warmup + {args.steps} timed solves")
     t_mixed, res_m, Dh = time_solve(gcp, H, w, args.steps, args.warmup, precision=prec,
                                     tol_ddbar=tol, max_iter=100, fold_every=args.fold_every,
@@ -440,37 +479,11 @@ def main() -> int:
     verify = {"ms": q["ms"], "trace_err": abs(q["trace"] - N), "fro2_minus_N": q["fro2"] - N,
               "idem": q["idem"], "energy_err": q["energy"] - e0, "comm": q["comm"]}
 
-    bwd = None
-    if args.bwd_steps > 0:
-        log(f"[bench] adjoint of the {prec.name} solve (FP32): {args.bwd_steps} timed")
-        ctx = gcp.Context(M, precision=prec, tol_ddbar=tol, max_iter=100,
-                          fold_every=args.fold_every, profile=True, keep_iterates=True,
-                          bwd_precision="fp32")
-        ctx.init(H, N, w.emin, w.emax)
-        ctx.purify()
-        u = torch.from_numpy(np.random.default_rng(33).standard_normal(M)).cuda()
-        G = torch.outer(u, u)
-        ctx.backward(G)   # warm-up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.bwd_steps):
-            _, rb = ctx.backward(G)
-        torch.cuda.synchronize()
-        tb = (time.perf_counter() - t0) / args.bwd_steps
-        ctx.close()
-        del G
-        bwd = {"precision": "fp32", "updates": rb.iters, "ms": tb * 1e3,
-               "tflops": rb.gemm_flops / tb / 1e12,
-               "gemm_ms_per_launch": rb.gemm_ms / max(rb.gemm_launches, 1),
-               "gemm_frac_of_fp32_peak": rb.gemm_flops / (rb.gemm_ms * 1e-3) / 1e12
-               / PEAK_TFLOPS["fp32"]}
-        log(f"[bench] adjoint: {tb*1e3:.1f} ms, {bwd['tflops']:.1f} TFLOP/s")
+    bwd = time_adjoint(gcp, H, w, prec, tol, args) if args.bwd_steps > 0 else None
     del H, D_ref
 
     extra = None if args.no_extra or args.scale != 1 else extra_configs(gcp, args)
 
-    if args.copy_calibration:
-        copy_calibration()
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -212,16 +212,20 @@ int gcp_purify(gcp_ctx *ctx, void *D, int32_t dtype, int64_t ldd, gcp_result *ou
  * M x M, leading dimension ldg, dtype gcp_dtype; read as its symmetric part),
  * writes dL/dH (device, M x M, leading dimension ldh, same dtype), the
  * gradient with respect to symmetric perturbations of H, for the p updates
- * that gcp_purify applied, whatever its status.  Supported for the HPCP
- * recursion with the PMCP or the fixed-alpha hole-particle guess; the PMCP
- * recursion and the alpha search return UNSUPPORTED.
- *   - Each update of eq. (hpcp3), D' = (1-2c) D + (2+2c) D^2 - 2 D^3 with
- *     c = (T2 - T3)/(T1 - T2), is differentiated including the dependence of
- *     c on D; this costs two symmetric and two general M x M products per
- *     update (about three times the forward).
- *   - The initial guess of eqs. (dmguess),(pmcpguess) is differentiated
- *     through mu = Tr(H)/M and beta(mu), with emin/emax held fixed (also when
- *     they were Gershgorin bounds derived from H).
+ * that gcp_purify applied, whatever its status.  Every recursion, initial
+ * guess and hole option is supported.
+ *   - Each update, D' = a D + b D^2 + e D^3 with (a, b, e) functions of
+ *     c = (T2 - T3)/(T1 - T2) (eq. (hpcp3), or eqs. (pm1a)/(pm1b) for PMCP),
+ *     is differentiated including the dependence of c on D; this costs two
+ *     symmetric and two general M x M products per update (about three
+ *     times the forward).
+ *   - The initial guess is differentiated through mu = Tr(H)/M and the
+ *     slope beta: beta(mu) of eqs. (dmguess),(pmcpguess) or of the
+ *     fixed-alpha guess of eq. (hpcpguess), with emin/emax held fixed (also
+ *     when they were Gershgorin bounds derived from H); for the alpha
+ *     search of eq. (hpcpguessalpha) (alpha strictly inside (0, 1)), beta
+ *     through ||mu I - H||_F.  A searched alpha that fell back to 1 or was
+ *     clamped to 0 or 1 is differentiated as that fixed alpha.
  *   - N = 0 or N = M gives dL/dH = 0 (D_0 does not depend on H).
  * The stored iterates stay valid for repeated calls (several loss gradients).
  * out may be NULL; out->iters = p, out->gemm_* count the adjoint products and

@@ -106,6 +106,7 @@ struct gcp_ctx {
   double mu = NAN, beta = NAN, emin = NAN, emax = NAN, alpha = 1.0;
   double beta_min = 0.0, beta_max = 0.0;
   bool alpha_searched = false;   // alpha from the search's target (depends on H)
+  double hdev = 0.0;             // ||mu I - H||_F^2 when alpha_searched
   double t1_0 = NAN, t2_0 = NAN;
   void *D0p = nullptr;      // copy of the D_0 planes so purify can be re-run
   double *dg0 = nullptr, *rD0 = nullptr, *d20 = nullptr;
@@ -123,7 +124,7 @@ struct gcp_ctx {
   int bwd_p = -1;           // updates covered by the stored iterates (-1: none)
   void *bG[2] = {nullptr, nullptr};
   void *bX2 = nullptr, *bAT = nullptr, *bCT = nullptr;
-  double *btpart = nullptr; // upper-tile partial sums
+  double *btpart = nullptr; // per-tile partial sums of kappa (2 ntri + nt^2)
   double *bvec = nullptr;   // 2 Mp row scratch + kappa + 2 sums
   // verification workspace (allocated by the first gcp_verify)
   double *vD = nullptr, *vH = nullptr, *vHD = nullptr, *vaux = nullptr;
@@ -365,7 +366,7 @@ static void for_each_buffer(gcp_ctx *c, bool one_shot, F &&f) {
     f(&c->bX2, bb);
     f(&c->bAT, bb);
     f(&c->bCT, bb);
-    f((void **)&c->btpart, (size_t)c->nt * (c->nt + 1) / 2 * sizeof(double));
+    f((void **)&c->btpart, ((size_t)c->nt * (c->nt + 1) + (size_t)c->nt * c->nt) * sizeof(double));
     f((void **)&c->bvec, (2 * Mp + 8) * sizeof(double));
   }
 }
@@ -575,6 +576,7 @@ extern "C" int gcp_init(gcp_ctx *c, const double *H, int64_t ldh, int64_t N, dou
                                  c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         const double S = c->sc_host->hstat[3];
+        c->hdev = S;
         const double b2 = (target - (double)N * theta) / S;
         if (!(b2 > 0.0) || !(S > 0.0)) {
           alpha = 1.0;
@@ -1012,10 +1014,6 @@ extern "C" int gcp_backward(gcp_ctx *c, const void *dLdD, int64_t ldg, void *dLd
     c->err = "gcp_backward: needs a gcp_purify with keep_iterates = 1 after the last gcp_init";
     return GCP_ERR_STATE;
   }
-  if (c->opt.method != GCP_METHOD_HPCP || c->alpha_searched) {
-    c->err = "gcp_backward: the adjoint covers the HPCP recursion with a fixed-alpha guess";
-    return GCP_ERR_UNSUPPORTED;
-  }
   if (!dLdD || !dLdH || ldg < c->M || ldh < c->M ||
       (dtype != GCP_DTYPE_F64 && dtype != GCP_DTYPE_F32)) {
     c->err = "gcp_backward: need non-NULL buffers, ldg >= M, ldh >= M and dtype F64 or F32";
@@ -1079,24 +1077,26 @@ extern "C" int gcp_backward(gcp_ctx *c, const void *dLdD, int64_t ldg, void *dLd
     }
     const double *h = c->hist_host.data() + (size_t)n * GCP_HIST_COLS;
     const double cn = h[4], t12 = h[1] - h[2];
+    double da, db, de;
+    update_coefs(c->opt.method, cn, a.a, a.b, a.e);
+    update_coef_derivs(c->opt.method, cn, da, db, de);
     a.D = c->slots[n - n0];
     a.G = c->bG[cur];
-    a.a = 1.0 - 2.0 * cn;
-    a.b = 2.0 + 2.0 * cn;
     a.c = cn;
     a.inv_t12 = 1.0 / t12;
-    // X2 = D D and the partial sums of kappa
+    a.need_x3 = de != 0.0;
+    // X2 = D D and the partial sums of <G, D^2> and <G, D>
     a.mode = 0;
     a.out0 = c->bX2;
     int st = gemm(a);
     if (st != GCP_OK) return st;
-    HIPCHK(c, launch_bwd_kappa(c->btpart, ntri, kappa, c->stream));
-    // AT = D G, CT = X2 G
+    // AT = D G, CT = X2 G (and the partial sums of <G, D^3> = <X2, AT>)
     a.mode = 1;
     a.out0 = c->bAT;
     a.out1 = c->bCT;
     st = gemm(a);
     if (st != GCP_OK) return st;
+    HIPCHK(c, launch_bwd_kappa(c->btpart, ntri, c->nt * c->nt, da, db, de, kappa, c->stream));
     // Gbar_n
     a.mode = 2;
     a.out0 = c->bG[1 - cur];
@@ -1113,7 +1113,8 @@ extern "C" int gcp_backward(gcp_ctx *c, const void *dLdD, int64_t ldg, void *dLd
   ia.theta = (double)c->N / (double)c->M;
   ia.beta = c->beta;
   ia.dbeta = 0.0;
-  if (c->N > 0 && c->N < c->M) {
+  ia.hdev = c->alpha_searched ? c->hdev : 0.0;
+  if (c->N > 0 && c->N < c->M && !c->alpha_searched) {
     // beta = alpha beta_min + (1 - alpha) beta_max with alpha fixed; each
     // branch differentiated through mu with the bounds held fixed
     const double bt = ia.theta / (c->emax - c->mu), bb = (1.0 - ia.theta) / (c->mu - c->emin);

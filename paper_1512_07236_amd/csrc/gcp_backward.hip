@@ -1,20 +1,25 @@
 // gcp_backward.hip -- adjoint of the purification (reverse mode), gfx950.
 //
-// Given Gbar_p = dL/dD_p of the returned matrix, the update of eq. (hpcp3),
-// D' = a D + b D^2 - 2 D^3 with a = 1 - 2c, b = 2 + 2c and
-// c = (T2 - T3)/(T1 - T2), is differentiated by hand for symmetric D and
-// Gbar' (= dL/dD'):
+// Given Gbar_p = dL/dD_p of the returned matrix, every update
+// D' = a D + b D^2 + e D^3, with (a, b, e) functions of
+// c = (T2 - T3)/(T1 - T2) (eq. (hpcp3): 1 - 2c, 2 + 2c, -2; eqs.
+// (pm1a)/(pm1b) for PMCP; update_coefs), is differentiated by hand for
+// symmetric D and Gbar' (= dL/dD'):
 //
-//   Gbar = a Gbar' + b (D Gbar' + Gbar' D) - 2 (D^2 Gbar' + Gbar' D^2 + D Gbar' D)
+//   Gbar = a Gbar' + b (D Gbar' + Gbar' D) + e (D^2 Gbar' + Gbar' D^2 + D Gbar' D)
 //          + kappa [(2 D - 3 D^2) - c (I - 2 D)] / (T1 - T2),
-//   kappa = 2 <Gbar', D^2 - D>   (Frobenius product; dD'/dc = 2 (D^2 - D)).
+//   kappa = <Gbar', dD'/dc> = a' <Gbar', D> + b' <Gbar', D^2> + e' <Gbar', D^3>
+//
+// (Frobenius products; a', b', e' from update_coef_derivs; <Gbar', D^3> =
+// <D^2, D Gbar'>, needed only when e' != 0, i.e. for PMCP).
 //
 // One adjoint step is three launches of 128 x 128 MFMA tile products, all of
 // the A * B^T row-panel form of the forward (every operand is symmetric
 // except AT and CT, which are only ever read along their rows):
 //   mode 0 (upper tiles)  X2 = D D           epilogue: per-tile sums of
-//                                            w_ij Gbar'_ij (X2_ij - D_ij)
-//   mode 1 (all tiles)    AT = D Gbar'  and  CT = X2 Gbar'   (one launch)
+//                                            w_ij Gbar'_ij X2_ij and w_ij Gbar'_ij D_ij
+//   mode 1 (all tiles)    AT = D Gbar'  and  CT = X2 Gbar'   (one launch;
+//                                            PMCP: per-tile sums of X2 o AT)
 //   mode 2 (upper tiles)  E  = D (Gbar' D)   epilogue: Gbar_n from Gbar', AT,
 //                                            AT^T, CT, CT^T, E, D and X2
 // with AT + AT^T = D Gbar' + Gbar' D and CT + CT^T = D^2 Gbar' + Gbar' D^2.
@@ -22,11 +27,16 @@
 // output) and two general ones (2 M^3 each).  kappa is reduced on the device
 // in a fixed order, so the whole backward is bitwise reproducible.
 //
-// The initial guess of eqs. (dmguess),(pmcpguess), D_0 = theta I + beta(mu)
-// (mu I - H) with mu = Tr(H)/M and the spectral bounds held fixed, gives
+// The initial guess D_0 = theta I + beta (mu I - H), mu = Tr(H)/M.  With a
+// fixed slope rule (eqs. (dmguess),(pmcpguess), or eq. (hpcpguess) with a
+// fixed alpha) and the spectral bounds held fixed,
 //   dL/dH = -beta Gbar_0 + (I/M) [beta Tr Gbar_0 + beta'(mu) <Gbar_0, mu I - H>],
 // where <Gbar_0, mu I - H> = (<Gbar_0, D_0> - theta Tr Gbar_0) / beta, so H is
-// not needed again, and beta' belongs to the active branch of the min.
+// not needed again, and beta' belongs to the active branch of the min.  The
+// alpha search of eq. (hpcpguessalpha) sets beta = sqrt((target - N theta)/S)
+// with S = ||mu I - H||_F^2 (alpha strictly inside (0, 1)); then beta' = 0
+// and d beta = (beta / S) <mu I - H, dH> adds
+//   (<Gbar_0, mu I - H> / S) (D_0 - theta I)     (= (beta <Gbar_0, g>/S) g).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -100,6 +110,8 @@ __global__ __launch_bounds__(NTH, 2) void k_bgemm(BwdArgs a) {
 
   if constexpr (MODE == 1) {
     T *__restrict__ O = (T *)(which ? a.out1 : a.out0);
+    const bool x3 = a.need_x3 && !which;   // block-uniform
+    double xsum = 0.0;
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
@@ -108,14 +120,30 @@ __global__ __launch_bounds__(NTH, 2) void k_bgemm(BwdArgs a) {
         for (int r = 0; r < 4; ++r) {
           const int64_t i = arow0 + wm * 64 + bi * 16 + acc_row<KIND>(lg, r);
           const int64_t j = brow0 + wn * 64 + bj * 16 + l16;
-          O[i * Mp + j] = (T)acc[bi][bj][r];
+          const T o = (T)acc[bi][bj][r];
+          O[i * Mp + j] = o;
+          if (x3) xsum += (double)X2[i * Mp + j] * (double)o;
         }
+    if (x3) {
+      xsum += shfl_xor_d(xsum, 1);
+      xsum += shfl_xor_d(xsum, 2);
+      xsum += shfl_xor_d(xsum, 4);
+      xsum += shfl_xor_d(xsum, 8);
+      xsum += shfl_xor_d(xsum, 16);
+      xsum += shfl_xor_d(xsum, 32);
+      if (lane == 0) red[wave] = xsum;
+      __syncthreads();
+      if (tid == 0) {
+        const int ntri = a.nt * (a.nt + 1) / 2;
+        a.tpart[2 * ntri + ti * a.nt + tj] = ((red[0] + red[1]) + red[2]) + red[3];
+      }
+    }
     return;
   }
 
   const bool diag_tile = (ti == tj);
   T *__restrict__ O = (T *)a.out0;
-  double tsum = 0.0;
+  double tsum = 0.0, dsum = 0.0;
   const double kappa = MODE == 2 ? *a.kappa : 0.0;
 #pragma unroll
   for (int bi = 0; bi < 4; ++bi)
@@ -131,45 +159,65 @@ __global__ __launch_bounds__(NTH, 2) void k_bgemm(BwdArgs a) {
         double o;
         if constexpr (MODE == 0) {
           o = v;
-          const double w = (i == j) ? 1.0 : 2.0;
-          tsum += w * (double)G[i * Mp + j] * ((double)(T)v - d);
+          const double wg = ((i == j) ? 1.0 : 2.0) * (double)G[i * Mp + j];
+          tsum += wg * (double)(T)v;
+          dsum += wg * d;
         } else {
           const double g = (double)G[i * Mp + j];
           const double x2 = (double)X2[i * Mp + j];
           const double at = (double)AT[i * Mp + j] + (double)AT[j * Mp + i];
           const double ct = (double)CT[i * Mp + j] + (double)CT[j * Mp + i];
           const double gc = ((2.0 * d - 3.0 * x2) - a.c * ((i == j ? 1.0 : 0.0) - 2.0 * d)) * a.inv_t12;
-          o = a.a * g + a.b * at - 2.0 * (ct + v) + kappa * gc;
+          o = a.a * g + a.b * at + a.e * (ct + v) + kappa * gc;
         }
         O[i * Mp + j] = (T)o;
         if (i != j) O[j * Mp + i] = (T)o;
       }
 
   if constexpr (MODE == 0) {
-    tsum += shfl_xor_d(tsum, 1);
-    tsum += shfl_xor_d(tsum, 2);
-    tsum += shfl_xor_d(tsum, 4);
-    tsum += shfl_xor_d(tsum, 8);
-    tsum += shfl_xor_d(tsum, 16);
-    tsum += shfl_xor_d(tsum, 32);
-    if (lane == 0) red[wave] = tsum;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+      tsum += shfl_xor_d(tsum, m);
+      dsum += shfl_xor_d(dsum, m);
+    }
+    __shared__ double red2[4];
+    if (lane == 0) {
+      red[wave] = tsum;
+      red2[wave] = dsum;
+    }
     __syncthreads();
-    if (tid == 0) a.tpart[lin] = ((red[0] + red[1]) + red[2]) + red[3];
+    if (tid == 0) {
+      const int ntri = a.nt * (a.nt + 1) / 2;
+      a.tpart[lin] = ((red[0] + red[1]) + red[2]) + red[3];
+      a.tpart[ntri + lin] = ((red2[0] + red2[1]) + red2[2]) + red2[3];
+    }
   }
 }
 
-// kappa = 2 sum_t tpart[t] in a fixed order (one block).
-__global__ __launch_bounds__(256) void k_bkappa(const double *tpart, int n, double *kappa) {
-  __shared__ double s[256];
+// Sum of tpart[t0 .. t1) in a fixed order by the 256 threads of one block.
+__device__ double block_sum(const double *tpart, int t0, int t1, double *s) {
   double v = 0.0;
-  for (int t = threadIdx.x; t < n; t += 256) v += tpart[t];
+  for (int t = t0 + (int)threadIdx.x; t < t1; t += 256) v += tpart[t];
   s[threadIdx.x] = v;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *kappa = 2.0 * s[0];
+  const double r = s[0];
+  __syncthreads();
+  return r;
+}
+
+// kappa = da <G, D> + db <G, D^2> + de <G, D^3> from the per-tile sums, in a
+// fixed order (one block).
+__global__ __launch_bounds__(256) void k_bkappa(const double *tpart, int ntri, int nfull,
+                                                double da, double db, double de, double *kappa) {
+  __shared__ double s[256];
+  const double sx2 = block_sum(tpart, 0, ntri, s);
+  const double sd = block_sum(tpart, ntri, 2 * ntri, s);
+  const double sx3 = de != 0.0 ? block_sum(tpart, 2 * ntri, 2 * ntri + nfull, s) : 0.0;
+  if (threadIdx.x == 0) *kappa = da * sd + db * sx2 + de * sx3;
 }
 
 // Iterate D_n of the forward (operand planes of encoding PF plus the exact
@@ -274,14 +322,16 @@ __global__ __launch_bounds__(256) void k_bdh(BwdInitArgs a) {
   const int64_t i = blockIdx.x;
   const int64_t j = (int64_t)blockIdx.y * 256 + threadIdx.x;
   if (j >= a.M) return;
-  double s = 0.0;
+  double s = 0.0, k = 0.0;
   if (a.beta != 0.0) {
     const double gd = a.sums[0], tr = a.sums[1];
     const double g_muh = (gd - a.theta * tr) / a.beta;   // <G0, mu I - H>
     s = (a.beta * tr + a.dbeta * g_muh) / (double)a.M;
+    if (a.hdev > 0.0) k = g_muh / a.hdev;               // alpha-searched slope
   }
   double x = -a.beta * (double)((const TB *)a.G0)[i * a.Mp + j];
-  if (i == j) x += s;
+  if (k != 0.0) x += k * (double)((const TB *)a.D0)[i * a.Mp + j];
+  if (i == j) x += s - k * a.theta;
   x *= a.sign;
   if (a.dtype == GCP_DTYPE_F64)
     ((double *)a.dH)[i * a.ldh + j] = x;
@@ -346,8 +396,9 @@ hipError_t launch_bwd_gemm(int bprec, const BwdArgs &a, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_bwd_kappa(const double *tpart, int n, double *kappa, hipStream_t st) {
-  k_bkappa<<<1, 256, 0, st>>>(tpart, n, kappa);
+hipError_t launch_bwd_kappa(const double *tpart, int ntri, int nfull, double da, double db,
+                            double de, double *kappa, hipStream_t st) {
+  k_bkappa<<<1, 256, 0, st>>>(tpart, ntri, nfull, da, db, de, kappa);
   return hipGetLastError();
 }
 

@@ -17,6 +17,51 @@ __host__ __device__ inline int fp32_fold(int64_t Mp) {
   return r < 1 ? 1 : r;
 }
 
+// D' = a D + b D^2 + e D^3 for the recursion `method` at coefficient c:
+// HPCP, eq. (hpcp3) with Dbar = I - D: a = 1 - 2c, b = 2 + 2c, e = -2;
+// PMCP, eq. (pm1a) for c <= 1/2: (1 - 2c, 1 + c, -1) / (1 - c),
+//       eq. (pm1b) for c > 1/2:  (0, 1 + c, -1) / c.
+// Every choice keeps a Tr D + b Tr D^2 + e Tr D^3 = Tr D for this c.
+__host__ __device__ inline void update_coefs(int method, double c, double &a, double &b,
+                                             double &e) {
+  if (method == 0) {
+    a = 1.0 - 2.0 * c;
+    b = 2.0 + 2.0 * c;
+    e = -2.0;
+  } else if (c <= 0.5) {
+    const double r = 1.0 / (1.0 - c);
+    a = (1.0 - 2.0 * c) * r;
+    b = (1.0 + c) * r;
+    e = -r;
+  } else {
+    const double r = 1.0 / c;
+    a = 0.0;
+    b = (1.0 + c) * r;
+    e = -r;
+  }
+}
+
+// Derivatives of (a, b, e) above with respect to c (the adjoint's
+// dD'/dc = a' D + b' D^2 + e' D^3).
+__host__ __device__ inline void update_coef_derivs(int method, double c, double &da, double &db,
+                                                   double &de) {
+  if (method == 0) {
+    da = -2.0;
+    db = 2.0;
+    de = 0.0;
+  } else if (c <= 0.5) {
+    const double r = 1.0 / (1.0 - c);
+    da = -r * r;
+    db = 2.0 * r * r;
+    de = -r * r;
+  } else {
+    const double r = 1.0 / c;
+    da = 0.0;
+    db = -r * r;
+    de = r * r;
+  }
+}
+
 // Device-resident scalars of one solve (FP64 traces and the decision).
 struct Scalars {
   double t1, t2, t3, omega, c, step;
@@ -111,9 +156,13 @@ struct BwdArgs {
   int64_t Mp;
   int nt;
   int mode;            // 0: X2 = D D; 1: AT = D G and CT = X2 G; 2: E = D G D + combine
-  double a, b, c, inv_t12;   // 1 - 2c_n, 2 + 2c_n, c_n, 1 / (T1 - T2)_n
+  int need_x3;         // mode 1: also the per-tile sums of X2 o AT (<G, D^3>; e' != 0)
+  double a, b, e;      // D_{n+1} = a D + b D^2 + e D^3 at c_n (update_coefs)
+  double c, inv_t12;   // c_n, 1 / (T1 - T2)_n
   const double *kappa; // device scalar (mode 2)
-  double *tpart;       // mode 0: per-tile sums of w_ij G_ij (X2_ij - D_ij)
+  double *tpart;       // per-tile sums: [0, ntri) w_ij G_ij X2_ij and [ntri, 2 ntri)
+                       // w_ij G_ij D_ij over upper tiles (mode 0), [2 ntri, 2 ntri + nt^2)
+                       // X2 o AT over all tiles (mode 1, need_x3)
 };
 
 struct BwdInitArgs {
@@ -121,6 +170,7 @@ struct BwdInitArgs {
   const void *D0;      // D_0 (Mp x Mp)
   int64_t M, Mp, ldh;
   double beta, dbeta, theta;
+  double hdev;         // alpha-searched guess: ||mu I - H||_F^2 (0: alpha fixed)
   double sign;         // -1 for the hole recursion (dL/dDbar = -dL/dD)
   double *rows;        // 2 Mp scratch: row sums of G0 o D0, diag of G0
   double *sums;        // 2 scalars
@@ -146,7 +196,8 @@ hipError_t launch_bwd_store(int fprec, int bprec, const void *planes, const doub
 hipError_t launch_bwd_load(int bprec, const void *g, int64_t ldg, int dtype, int64_t M,
                            int64_t Mp, void *G, hipStream_t st);
 hipError_t launch_bwd_gemm(int bprec, const BwdArgs &a, hipStream_t st);
-hipError_t launch_bwd_kappa(const double *tpart, int n, double *kappa, hipStream_t st);
+hipError_t launch_bwd_kappa(const double *tpart, int ntri, int nfull, double da, double db,
+                            double de, double *kappa, hipStream_t st);
 hipError_t launch_bwd_init(int bprec, const BwdInitArgs &a, hipStream_t st);
 
 hipError_t launch_gemm(int prec, const GemmArgs &g, hipStream_t st);

@@ -23,30 +23,6 @@
 
 namespace gcp {
 
-// D' = a D + b D^2 + e D^3 for the recursion `method` at coefficient c:
-// HPCP, eq. (hpcp3) with Dbar = I - D: a = 1 - 2c, b = 2 + 2c, e = -2;
-// PMCP, eq. (pm1a) for c <= 1/2: (1 - 2c, 1 + c, -1) / (1 - c),
-//       eq. (pm1b) for c > 1/2:  (0, 1 + c, -1) / c.
-// Every choice keeps a Tr D + b Tr D^2 + e Tr D^3 = Tr D for this c.
-__device__ __forceinline__ void update_coefs(int method, double c, double &a, double &b,
-                                             double &e) {
-  if (method == 0) {
-    a = 1.0 - 2.0 * c;
-    b = 2.0 + 2.0 * c;
-    e = -2.0;
-  } else if (c <= 0.5) {
-    const double r = 1.0 / (1.0 - c);
-    a = (1.0 - 2.0 * c) * r;
-    b = (1.0 + c) * r;
-    e = -r;
-  } else {
-    const double r = 1.0 / c;
-    a = 0.0;
-    b = (1.0 + c) * r;
-    e = -r;
-  }
-}
-
 // FP64 / FP32 product kernel: one 128 x 128 upper-triangle tile per block of
 // 4 waves (2 x 2 grid of 64 x 64), MFMA 16x16x4, two blocks per CU.
 template <int P>

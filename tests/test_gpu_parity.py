@@ -295,6 +295,23 @@ def test_full_size_spectral_8192(config3, precision, tol_ddbar, err_tol):
     assert np.all(dt3 <= cnum)
 
 
+
+def test_full_size_fold_against_one_accumulator(config3):
+    """M = 8192, FP16X3: the chunked accumulation is what brings the error
+    down.  Per output element the product runs 256 K stages of 3 MFMA
+    products; one accumulator rounds each term about 3 x 256 = 768 times, the
+    default fold (every sqrt(256 / 3) = 9 stages) about 3 x 9 + 256 / 9 = 56
+    times, a factor sqrt(768 / 56) = 3.7 in the accumulated rounding.  The
+    error of the whole solve must shrink by at least half that."""
+    w, ref, _ = config3
+    errs = {}
+    for fold in (0, 1000):
+        D, res = run_gpu(w, "fp16x3", tol_ddbar=1e-5, fold_every=fold)
+        assert res.status in gcp.SUCCESS
+        errs[fold] = rel_err(D, ref)
+        log(f"  fp16x3 fold={fold}: iters={res.iters} err={errs[fold]:.3e}")
+    assert errs[0] < errs[1000] / (3.7 / 2)
+
 # ------------------------------------------------------- precision schedule
 
 def _ctx_run(w, **opts):

@@ -2,7 +2,8 @@
 the Palser-Manolopoulos canonical purification (eqs. (pm1a)/(pm1b)), the
 hole-particle guess of eq. (hpcpguess) with a fixed alpha, its alpha search
 (eq. (hpcpguessalpha)) and the fall-back to the PMCP guess; the Fig. 3
-protocol's iteration counts seed by seed; the adjoint of the fixed-alpha guess.
+protocol's iteration counts seed by seed; the adjoint of every guess and of
+both recursions.
 
 FP64 runs are compared element by element with oracle.purify_ex on the same
 input bytes (same iteration count and alpha, c_n to the conditioning of
@@ -117,7 +118,7 @@ def test_mixed_precision_with_the_alpha_search():
     assert np.abs(res.col("t1") - w.N).max() < 1e-10
 
 
-def test_adjoint_of_the_fixed_alpha_guess_and_unsupported_cases():
+def test_adjoint_of_the_fixed_alpha_guess():
     w = workloads.spectral(256, 100, 0.2, 72)
     Gp = workloads.sym_gaussian(256, 272)
     with gcp.Context(256, init="hp", alpha=0.5, keep_iterates=True, tol_ddbar=1e-6) as ctx:
@@ -130,14 +131,45 @@ def test_adjoint_of_the_fixed_alpha_guess_and_unsupported_cases():
     err = float(np.abs(dH - ref).max() / np.abs(ref).max())
     log(f"  hp adjoint p={res.iters} err={err:.2e}")
     assert err < 1e-9
-    for opts in ({"method": "pmcp"}, {"init": "search"}):
-        w2 = workloads.spectral(256, 13, 0.2, 73)   # theta = 0.05: the search picks alpha
-        with gcp.Context(256, keep_iterates=True, tol_ddbar=1e-6, **opts) as ctx:
-            ctx.init(to_gpu(w2.H), w2.N, w2.emin, w2.emax)
-            ctx.purify()
-            with pytest.raises(gcp.GCPError) as e:
-                ctx.backward(to_gpu(Gp))
-            assert e.value.status == gcp.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("opts,N", [({"method": "pmcp"}, 100),
+                                    ({"init": "search"}, 13),
+                                    ({"method": "pmcp", "init": "search"}, 13),
+                                    ({"method": "pmcp", "init": "search"}, 243),
+                                    ({"init": "search", "hole": True}, 13)])
+def test_adjoint_of_pmcp_and_the_alpha_search(opts, N):
+    """FP64 adjoint of the PMCP recursion (eqs. (pm1a)/(pm1b)) and of the
+    alpha-searched guess (eq. (hpcpguessalpha)) against the oracle's adjoint
+    (pinned by finite differences) at the GPU's p.  PMCP at theta = 0.39
+    passes through both branches of c; the search picks alpha inside (0, 1)
+    at theta = 0.05 (c <= 1/2 throughout) and 0.95 (c > 1/2 throughout).  The
+    HPCP hole run's adjoint equals the particle run's (HPCP is hole-particle
+    symmetric), so the search term is also checked through the hole
+    recursion's sign flips."""
+    w = workloads.spectral(256, N, 0.2, 73)
+    Gp = workloads.sym_gaussian(256, 272)
+    log(f"[gpu] adjoint {opts}")
+    with gcp.Context(256, keep_iterates=True, tol_ddbar=1e-6, **opts) as ctx:
+        ctx.init(to_gpu(w.H), w.N, w.emin, w.emax)
+        _, res = ctx.purify(raise_on_failure=True)
+        alpha = ctx.init_scalars()["alpha"]
+        dH, _ = ctx.backward(to_gpu(Gp))
+        dH = dH.cpu().numpy()
+    method = opts.get("method", "hpcp")
+    init = opts.get("init")
+    if init == "search":
+        *_, a_ref, searched = grad.guess(w.H, w.N, w.emin, w.emax, init="search")
+        assert searched and abs(alpha - a_ref) < 1e-9
+    ref = grad.adjoint(w.H, w.N, w.emin, w.emax, res.iters, Gp, method=method, init=init)
+    _, cs, *_ = grad.forward_iterates(w.H, w.N, w.emin, w.emax, res.iters, method=method,
+                                      init=init)
+    err = float(np.abs(dH - ref).max() / np.abs(ref).max())
+    log(f"  p={res.iters} alpha={alpha:.4f} c>1/2 at {int(np.sum(cs > 0.5))} updates "
+        f"err={err:.2e}")
+    if method == "pmcp" and init is None:
+        assert np.any(cs > 0.5) and np.any(cs <= 0.5)
+    assert err < 1e-9
 
 
 @pytest.mark.parametrize("method", ["hpcp", "pmcp"])
