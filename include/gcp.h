@@ -164,10 +164,15 @@ typedef struct {
     double t1;           /* Tr D of the returned matrix (FP64) */
     double t2;           /* Tr D^2 (FP64) */
     double c_last;       /* last coefficient c_n used */
-    double idem;         /* ||D^2 - D||_F of the returned matrix (from the last D^2) */
+    double idem;         /* ||D^2 - D||_F of the returned matrix, when its square was
+                            formed: with tol_idem = 0 (default) a stop on Tr(D Dbar)
+                            (tolerance or rounding floor) is decided from the traces
+                            of the last update, the last square is never formed and
+                            idem is NaN (gcp_verify measures it in FP64) */
     double ms_total;     /* wall time of gcp_purify on the host clock (ms) */
     double gemm_ms;      /* summed device time of the matrix-product launches (profile=1) */
-    int32_t gemm_launches; /* number of matrix-product launches that did work */
+    int32_t gemm_launches; /* number of matrix-product launches that did work: 2p, or
+                              2p + 1 when the stop needed the square of D_p */
     int32_t host_syncs;  /* host synchronisations of the iteration loop (gcp_purify) */
     double gemm_flops;   /* algorithmic flops of those launches (M^3 per product,
                             upper-triangle output; split products not counted) */

@@ -433,7 +433,8 @@ extern "C" const char *gcp_last_error(const gcp_ctx *c) {
 
 static int reduce(gcp_ctx *c, const double *part, int nslots, int mode, double *out,
                   const double *extra, const double *tpart, int ntp, int iter,
-                  bool skip_if_stopped = false, double floor_ddbar = 0.0) {
+                  bool skip_if_stopped = false, double floor_ddbar = 0.0,
+                  bool early_stop = false) {
   RedArgs a{};
   a.part = part;
   a.nslots = nslots;
@@ -452,6 +453,7 @@ static int reduce(gcp_ctx *c, const double *part, int nslots, int mode, double *
   a.N = (double)(c->opt.hole ? c->M - c->N : c->N);   // trace of the purified matrix
   a.floor_ddbar = floor_ddbar;
   a.skip_if_stopped = skip_if_stopped ? 1 : 0;
+  a.early_stop = early_stop ? 1 : 0;
   a.sc = c->sc;
   a.hist = c->hist;
   HIPCHK(c, launch_reduce(a, c->stream));
@@ -742,8 +744,12 @@ static int step_k2(gcp_ctx *c, GemmArgs &g, int pi, int k, int n, LaunchLog *log
   g.rD_new = c->rD[1 - k];
   int st = run_product(c, g, pi, log);
   if (st != GCP_OK) return st;
+  // In the solve (not when a segment is recomputed for the adjoint) the
+  // stops that need only the new traces are decided here, unless the
+  // idempotency test, which needs the next square, is on.
+  const bool solve = g.status != nullptr;
   return reduce(c, c->part, c->nt, 2, c->d2[1 - k], c->dg[1 - k], c->tpart, c->pc[pi].ntpart, n,
-                g.status != nullptr);
+                solve, c->pc[pi].floor_ddbar, solve && !(c->opt.tol_idem > 0.0));
 }
 
 // Precision schedule: re-encode D_n (buffer k) and X2 = D_n^2 in pc[1]; the
@@ -961,9 +967,11 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
   if (status == 2) rc = GCP_ERR_NOT_CONVERGED;
   if (status == 3) rc = GCP_ERR_BREAKDOWN;
   if (status == 4) rc = GCP_STOPPED_AT_FLOOR;
-  // launches that did work: K1 of updates 0..p and K2 of 0..p-1 (any after
-  // them were enqueued past the stop and returned at once)
-  const int real = 2 * iters + 1 < lg.n ? 2 * iters + 1 : lg.n;
+  // launches that did work: K1 of updates 0..p (0..p-1 when the stop was
+  // decided from the traces of D_p) and K2 of 0..p-1 (any after them were
+  // enqueued past the stop and returned at once)
+  const int worked = 2 * iters + (c->sc_host->on_traces ? 0 : 1);
+  const int real = worked < lg.n ? worked : lg.n;
   if (res) {
     std::memset(res, 0, sizeof(*res));
     res->status = rc;

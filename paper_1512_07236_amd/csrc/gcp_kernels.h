@@ -70,6 +70,9 @@ struct Scalars {
   int32_t iter;     // update at which status became non-zero
   double hstat[4];  // Gershgorin min, max, Tr H
   double prev_ddbar;   // |Tr(D Dbar)| of the previous iterate (+inf before the first)
+  int32_t on_traces;   // 1: the stop was decided from the update's traces, before
+                       // the square of the last iterate was formed
+  int32_t pad;
 };
 
 struct GemmArgs {
@@ -125,7 +128,7 @@ struct RedArgs {
   const double *tpart;
   int ntiles;
   int iter, max_iter;
-  int pad;
+  int early_stop;      // mode 2: decide the stops that need only T1 and T2 of D_{n+1}
   double tol_ddbar, tol_idem, N;
   double floor_ddbar;  // rounding floor of |Tr(D Dbar)| of the encoding
   int skip_if_stopped; // 1: do nothing once sc->status is non-zero

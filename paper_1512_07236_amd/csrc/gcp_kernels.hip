@@ -1043,6 +1043,31 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
     sc->t1 = sum_extra;
     sc->step = sum_tiles;
     a.hist[(int64_t)a.iter * 9 + 8] = sqrt(sum_tiles);
+    if (!a.early_stop) return;
+    // The stops of the mode-1 decision that need only T1 and T2 of D_{n+1},
+    // taken here so that the square of the last iterate is never formed:
+    // |Tr(D Dbar)| within tol_ddbar, or within the rounding floor while not
+    // decreasing or not positive (below max_iter, where mode 1 would report
+    // max_iter first).  Everything else (non-finite traces, c outside
+    // [0, 1], max_iter) is left to mode 1, which would take the same
+    // decision on the same traces.
+    const double t1 = sum_extra, t2 = sum_out, ddbar = t1 - t2;
+    const int nx = a.iter + 1;
+    int status = 0;
+    if (isfinite(t1) && isfinite(t2)) {
+      if (fabs(ddbar) <= a.tol_ddbar) status = 1;
+      else if (nx < a.max_iter && (!(ddbar > 0.0) || fabs(ddbar) >= sc->prev_ddbar) &&
+               fabs(ddbar) <= a.floor_ddbar)
+        status = 4;
+    }
+    if (status == 0) return;
+    sc->status = status;
+    sc->iter = nx;
+    sc->on_traces = 1;
+    sc->omega = NAN;
+    double *h = a.hist + (int64_t)nx * 9;
+    h[0] = nx; h[1] = t1; h[2] = t2;
+    h[3] = h[4] = h[5] = h[6] = h[7] = h[8] = NAN;
   }
 }
 

@@ -39,25 +39,30 @@ def solve(w, **opts):
         return D.cpu().numpy(), res
 
 
+# (workload, options, whether the stop needs the square of the last iterate:
+# the idempotency test and max_iter are decided after it, a stop on
+# Tr(D Dbar) from the last update's traces)
 @pytest.mark.parametrize("case", [
-    ("chain", {"precision": "fp64", "tol_ddbar": 0.0, "tol_idem": 1e-10}),
-    ("spectral", {"precision": "fp16x3", "tol_ddbar": 1e-6}),
-    ("spectral", {"precision": "fp32", "tol_ddbar": 1e-6, "max_iter": 7}),
+    ("chain", {"precision": "fp64", "tol_ddbar": 0.0, "tol_idem": 1e-10}, True),
+    ("spectral", {"precision": "fp16x3", "tol_ddbar": 1e-6}, False),
+    ("spectral", {"precision": "fp32", "tol_ddbar": 1e-6, "max_iter": 7}, True),
     ("spectral", {"precision": "fp16x3", "late_precision": "fp64", "switch_ddbar": 1e-2,
-                  "tol_ddbar": 1e-10}),
+                  "tol_ddbar": 1e-10}, False),
 ])
 def test_sync_every_changes_nothing_but_the_host_syncs(case):
-    kind, opts = case
+    kind, opts, last_square = case
     w = workloads.config(1) if kind == "chain" else workloads.spectral(520, 200, 0.1, 61)
     D1, r1 = solve(w, sync_every=1, profile=True, **opts)
     p = r1.iters
-    assert r1.gemm_launches == 2 * p + 1
+    launches = 2 * p + (1 if last_square else 0)
+    assert r1.gemm_launches == launches
+    assert math.isnan(r1.idem) != last_square
     for k in (2, 3, 4, 7, 50):
         Dk, rk = solve(w, sync_every=k, profile=True, **opts)
         assert rk.status == r1.status and rk.iters == p
         assert np.array_equal(Dk, D1)
         assert np.array_equal(rk.history, r1.history, equal_nan=True)
-        assert rk.gemm_launches == 2 * p + 1   # void launches past the stop not counted
+        assert rk.gemm_launches == launches   # void launches past the stop not counted
         if "late_precision" not in opts:
             assert rk.host_syncs <= math.ceil((p + 1) / k), (k, rk.host_syncs, p)
         log(f"  sync_every={k}: p={p} host syncs {rk.host_syncs} (every update: {r1.host_syncs})")
@@ -81,3 +86,25 @@ def test_stop_at_the_rounding_floor(precision, M, N):
     assert err <= (1e-6 if precision == "fp16x3" else 1e-4)
     D0, r0 = solve(w, precision=precision, tol_ddbar=1e-11, max_iter=60, floor_ddbar=0.0)
     assert r0.status in (gcp.ERR_BREAKDOWN, gcp.ERR_NOT_CONVERGED)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp16x3", 1e-6), ("fp64", 1e-9), ("bf16x3", 1e-11)])
+def test_stop_on_the_last_traces_skips_only_the_last_square(precision, tol):
+    """A stop on Tr(D Dbar) (the tolerance, or the rounding floor while
+    Tr(D Dbar) stops decreasing) is decided from the traces of the last
+    update.  Forcing the square of the last iterate (an idempotency test that
+    never fires, tol_idem = 1e-300) must give the same status, p, D and
+    history except the last row's T3 and Omega, with one launch more."""
+    w = workloads.spectral(640, 234, 0.1, 63)
+    Da, ra = solve(w, precision=precision, tol_ddbar=tol, max_iter=60)
+    Db, rb = solve(w, precision=precision, tol_ddbar=tol, max_iter=60, tol_idem=1e-300)
+    log(f"  {precision}: status {ra.status} p={ra.iters} launches {ra.gemm_launches} / "
+        f"{rb.gemm_launches} idem {ra.idem} / {rb.idem:.2e}")
+    assert ra.status in gcp.SUCCESS
+    assert ra.status == rb.status and ra.iters == rb.iters
+    assert np.array_equal(Da, Db)
+    p = ra.iters
+    assert np.array_equal(ra.history[:p], rb.history[:p], equal_nan=True)
+    assert np.array_equal(ra.history[p, :3], rb.history[p, :3])
+    assert ra.gemm_launches == 2 * p and rb.gemm_launches == 2 * p + 1
+    assert math.isnan(ra.idem) and rb.idem >= 0.0

@@ -9,6 +9,8 @@ clear error.
 import ctypes
 import sys
 
+import math
+
 import numpy as np
 import pytest
 
@@ -63,7 +65,8 @@ def test_static_solve_equals_the_context_solve(cases):
         log(f"  M={M} {prec}: static status {st} p={r.iters}; context status {r_ref.status} "
             f"p={r_ref.iters}")
         assert st == r_ref.status and r.iters == r_ref.iters
-        assert r.t1 == r_ref.t1 and r.t2 == r_ref.t2 and r.idem == r_ref.idem
+        assert r.t1 == r_ref.t1 and r.t2 == r_ref.t2
+        assert r.idem == r_ref.idem or (math.isnan(r.idem) and math.isnan(r_ref.idem))
         assert torch.equal(D, D_ref)
 
 
