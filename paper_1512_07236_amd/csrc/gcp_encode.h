@@ -110,16 +110,18 @@ template <> struct Enc<GCP_FP16X3> {
 };
 
 // Element (i, j) of plane p in the padded Mp x Mp storage of an encoding.
-// Two-plane encodings interleave the planes in blocks of 32 columns, so that
-// the 32-column K slice of both planes of a row is one 128-byte segment:
+// Split encodings interleave their planes in blocks of 32 columns, so that
+// the 32-column K slice of every plane of a row is one contiguous segment
+// (128 bytes for two planes, 192 for three):
 //   [row i][block j/32][plane p][j % 32].
-// Other encodings keep each plane as a separate row-major matrix.
+// Single-plane encodings are one row-major matrix.
 template <int P>
 __host__ __device__ __forceinline__ int64_t eoff(int64_t i, int64_t j, int p, int64_t Mp) {
-  if constexpr (Enc<P>::NP == 2)
-    return i * (2 * Mp) + (j >> 5) * 64 + p * 32 + (j & 31);
+  constexpr int NP = Enc<P>::NP;
+  if constexpr (NP >= 2)
+    return i * (NP * Mp) + (j >> 5) * (32 * NP) + p * 32 + (j & 31);
   else
-    return (int64_t)p * Mp * Mp + i * Mp + j;
+    return i * Mp + j;
 }
 
 }  // namespace gcp

@@ -277,7 +277,7 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
     kbase = split * nk_all / g.nsplit;
     nk = (split + 1) * nk_all / g.nsplit - kbase;
   }
-  const int64_t Mp = g.Mp, PS = g.pstride;
+  const int64_t Mp = g.Mp;
   const int64_t arow0 = (int64_t)ti * TILE, brow0 = (int64_t)cpair * BR;
   const T *__restrict__ Ag = (const T *)g.A;
   const T *__restrict__ Bg = (const T *)g.B;
@@ -315,8 +315,8 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
         const int p = blk / ((AR + BR) / 16), gq = blk % ((AR + BR) / 16);
         const int R = gq * 16 + (lane >> 2);
         const int c = (lane & 3) ^ swz(R);
-        const T *src = (R < AR ? Ag + p * PS + (arow0 + R) * Mp : Bg + p * PS + (brow0 + R - AR) * Mp) +
-                       (int64_t)(kbase + kt) * KT + c * 8;
+        const T *src = (R < AR ? Ag + (arow0 + R) * (NP * Mp) : Bg + (brow0 + R - AR) * (NP * Mp)) +
+                       (int64_t)(kbase + kt) * (NP * KT) + p * KT + c * 8;
         __builtin_amdgcn_global_load_lds((const void *)src,
                                          (lds_void *)(st + (p * (AR + BR) + gq * 16) * KT), 16, 0, 0);
       }
