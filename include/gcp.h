@@ -145,7 +145,15 @@ typedef struct {
                               is formed, and launches enqueued past the stop do nothing, so
                               the iterates and the history do not depend on it.  A precision
                               schedule checks after every update until it has switched. */
-    int32_t pad2;
+    int32_t ksplit;        /* 16-bit encodings: split the K range of every tile pair over
+                              ksplit blocks (2..64), whose FP32 totals the last of them
+                              adds in FP64, in split order: the chunked accumulation is
+                              then combined in FP64 across K.  Each block accumulates
+                              K/ksplit, so a term passes through about 3 fold +
+                              stages/(ksplit fold) FP32 roundings instead of 3 fold +
+                              stages/fold, at the price of one 128 KB FP32 partial tile
+                              written and read per block.  0 or 1 (default): only the last
+                              partial round of pairs is split (for load balance). */
     double floor_ddbar;    /* rounding floor of |Tr(D Dbar)|: NaN (default) = derived by the
                               library from the encoding's unit roundoff and its accumulation
                               scheme, 20 rho N / M with rho = u_enc + 2 u_acc sqrt(kappa) (kappa:

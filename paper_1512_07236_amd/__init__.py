@@ -76,7 +76,7 @@ class Options(ctypes.Structure):
                 ("init_mode", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("delta", ctypes.c_double), ("hole", ctypes.c_int32),
                 ("checkpoint_every", ctypes.c_int32), ("sync_every", ctypes.c_int32),
-                ("pad2", ctypes.c_int32), ("floor_ddbar", ctypes.c_double)]
+                ("ksplit", ctypes.c_int32), ("floor_ddbar", ctypes.c_double)]
 
 
 METHODS = {"hpcp": 0, "pmcp": 1}           # the recursion
@@ -191,7 +191,7 @@ class Context:
                  keep_iterates: bool = False, bwd_precision="fp64", late_precision=None,
                  switch_ddbar: float = 0.0, method: str = "hpcp", init: str = "pmcp",
                  alpha: float = 0.5, delta: float = 2.0 / 3.0, hole: bool = False,
-                 checkpoint_every: int = 0, sync_every: int = 4,
+                 checkpoint_every: int = 0, sync_every: int = 4, ksplit: int = 0,
                  floor_ddbar: float = math.nan, stream=None):
         L = load_library()
         self._L = L
@@ -215,6 +215,7 @@ class Context:
         o.hole = 1 if hole else 0
         o.checkpoint_every = int(checkpoint_every)
         o.sync_every = int(sync_every)
+        o.ksplit = int(ksplit)
         o.floor_ddbar = float(floor_ddbar)
         self.options = o
         import torch

@@ -6,6 +6,7 @@
 // (the paper's test on Tr(D Dbar) is made before c_n is formed).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <mutex>
@@ -190,13 +191,22 @@ static void PrecCfgInit(gcp_ctx *c, int k) {
   // per row (64 K values of one plane, or 32 of both); three planes 32 K.
   const int nk = np <= 2 ? (int)(c->Mp * np / 64) : (int)(c->Mp / 32);
   const double per_stage = np == 1 ? 2.0 : (double)products(prec);
+  // every pair split along K over `ks` blocks (the ksplit option), each
+  // folding its own nk / ks stages
+  const int ks = elem_size(prec) == 2 && c->opt.ksplit >= 2 ? std::min(c->opt.ksplit, nk) : 1;
   int f = c->opt.fold_every;
   if (f <= 0)
-    f = prec == GCP_FP32 ? fp32_fold(c->Mp) : (int)std::lround(std::sqrt((double)nk / per_stage));
+    f = prec == GCP_FP32 ? fp32_fold(c->Mp)
+                         : (int)std::lround(std::sqrt((double)nk / ks / per_stage));
   q.fold = f < 1 ? 1 : f;
   q.nfull = pair_count(c->nt);
   q.nsplit = 1;
   if (elem_size(prec) != 2) return;
+  if (ks >= 2) {
+    q.nfull = 0;
+    q.nsplit = ks;
+    return;
+  }
   // Pairs are equal units of work, one resident block per CU: the last
   // partial round of np % CUs pairs would leave most CUs idle, so each of
   // those pairs is split along K over up to min(CUs / tail, 4) blocks (at
@@ -267,8 +277,9 @@ static int check_options(const gcp_options &o, int64_t M, ErrText &err) {
     err = "gcp_create: late_precision must be -1 or a precision, switch_ddbar >= 0";
     return GCP_ERR_INVALID_ARG;
   }
-  if (o.sync_every < 1 || !(std::isnan(o.floor_ddbar) || o.floor_ddbar >= 0.0)) {
-    err = "gcp_create: sync_every must be >= 1 and floor_ddbar NaN or >= 0";
+  if (o.sync_every < 1 || !(std::isnan(o.floor_ddbar) || o.floor_ddbar >= 0.0) ||
+      o.ksplit < 0 || o.ksplit > 64) {
+    err = "gcp_create: sync_every must be >= 1, ksplit in [0, 64] and floor_ddbar NaN or >= 0";
     return GCP_ERR_INVALID_ARG;
   }
   if (o.method < GCP_METHOD_HPCP || o.method > GCP_METHOD_PMCP || o.init_mode < GCP_INIT_PMCP ||
@@ -314,7 +325,7 @@ static void split_tail(const gcp_ctx *c, int &tail, int &smax) {
   smax = 1;
   for (int k = 0; k < c->nprec; ++k)
     if (c->pc[k].nsplit > 1) {
-      tail = pair_count(c->nt) - c->pc[k].nfull;
+      tail = std::max(tail, pair_count(c->nt) - c->pc[k].nfull);
       if (c->pc[k].nsplit > smax) smax = c->pc[k].nsplit;
     }
 }
@@ -495,7 +506,8 @@ static double rounding_floor(const gcp_ctx *c, int k) {
     const double stages = np <= 2 ? (double)c->Mp * np / 64.0 : (double)c->Mp / 32.0;
     const double per_stage = np == 1 ? 2.0 : (double)products(prec);
     const double f = (double)c->pc[k].fold;
-    kappa = 32.0 * per_stage * f + stages / f;
+    const double ks = c->pc[k].nfull == 0 ? (double)c->pc[k].nsplit : 1.0;   // ksplit
+    kappa = 32.0 * per_stage * f + stages / ks / f;
   }
   const double rho = u_enc + 2.0 * u_acc * std::sqrt(kappa);
   const double n_eff = (double)(c->opt.hole ? c->M - c->N : c->N);

@@ -272,8 +272,11 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
     pair_of_block(blockIdx.x, g.nt, ti, cpair, lin);
   } else {
     const int u = (int)blockIdx.x - g.nfull;
-    split = u % g.nsplit;
-    pair_of_block(g.nfull + u / g.nsplit, g.nt, ti, cpair, lin);
+    // split-major: the blocks in flight together work on the same K range
+    // of consecutive pairs, which share their panels as whole pairs do
+    const int ntail = ((int)gridDim.x - g.nfull) / g.nsplit;
+    split = u / ntail;
+    pair_of_block(g.nfull + u % ntail, g.nt, ti, cpair, lin);
     kbase = split * nk_all / g.nsplit;
     nk = (split + 1) * nk_all / g.nsplit - kbase;
   }
@@ -457,9 +460,8 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
     // arrive adds all of them in split order (so the sum does not depend on
     // the arrival order) and runs the epilogue.
     constexpr int NV = 4 * NBJ;   // float4 per thread
-    const int q = (int)blockIdx.x - g.nfull;
-    const int pair = q / g.nsplit;
-    float4 *wsp = (float4 *)g.ws + (int64_t)q * NV * NTH16;
+    const int pair = lin - g.nfull;  // index among the split pairs
+    float4 *wsp = (float4 *)g.ws + ((int64_t)pair * g.nsplit + split) * NV * NTH16;
 #pragma unroll
     for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
@@ -484,6 +486,7 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
 #pragma unroll
       for (int bj = 0; bj < NBJ; ++bj) {
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 4
         for (int s = 0; s < g.nsplit; ++s) {
           const float4 v = w0[((int64_t)s * NV + bi * NBJ + bj) * NTH16 + tid];
           a0 += v.x;

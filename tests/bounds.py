@@ -84,10 +84,12 @@ def padded(M: int) -> int:
     return (M + 255) // 256 * 256
 
 
-def accumulation_kappa(M: int, precision: str, fold_every: int = 0) -> int:
+def accumulation_kappa(M: int, precision: str, fold_every: int = 0, ksplit: int = 0) -> int:
     """Rounding steps a product term passes through in the library's
     accumulation scheme (worst case), for the launch configuration the
-    library chooses at size M."""
+    library chooses at size M.  ksplit >= 2 (16-bit encodings): every block
+    accumulates stages / ksplit and the blocks' totals meet in FP64, whose
+    rounding is below first order here."""
     Mp = padded(M)
     if precision == "fp64":
         return Mp + 1
@@ -101,22 +103,26 @@ def accumulation_kappa(M: int, precision: str, fold_every: int = 0) -> int:
     # K per stage: 64 values of one plane, or 32 values of every plane
     stages = Mp * np_ // 64 if np_ <= 2 else Mp // 32
     per_stage = 2 if np_ == 1 else PRODUCTS[precision]   # products per stage and element
-    fold = fold_every if fold_every > 0 else max(1, int(round(math.sqrt(stages / per_stage))))
-    fold = min(fold, stages)
+    ks = min(ksplit, stages) if ksplit >= 2 else 1
+    # the library rounds half away from zero (lround)
+    fold = fold_every if fold_every > 0 else max(1, int(math.floor(math.sqrt(stages / ks / per_stage) + 0.5)))
+    own = -(-stages // ks)   # stages of the longest split
+    fold = min(fold, own)
     terms = 32 * per_stage
-    return terms * fold + math.ceil(stages / fold) + 2
+    return terms * fold + math.ceil(own / fold) + 2
 
 
 def unit(precision: str) -> float:
     return U64 if precision == "fp64" else U32
 
 
-def product_bound(A: np.ndarray, B: np.ndarray, M: int, precision: str, fold_every: int = 0):
+def product_bound(A: np.ndarray, B: np.ndarray, M: int, precision: str, fold_every: int = 0,
+                  ksplit: int = 0):
     """Element-wise bound on |fl(A B) - A B| for the GPU product of two
     masters (off-diagonal elements), and P = |A| |B|."""
     u_enc, a_enc, u_drop = encoding(precision)
     P = np.abs(A) @ np.abs(B)
-    kappa = accumulation_kappa(M, precision, fold_every)
+    kappa = accumulation_kappa(M, precision, fold_every, ksplit)
     # 1.01: the split terms sum to at most (1 + 3 u_lvl) |a||b|
     rel = 1.01 * (2.0 * unit(precision) * kappa + u_drop)
     K = A.shape[0]
@@ -131,7 +137,7 @@ def product_bound(A: np.ndarray, B: np.ndarray, M: int, precision: str, fold_eve
 
 
 def step_bounds(D: np.ndarray, c: float, precision: str, fold_every: int = 0,
-                method: str = "hpcp"):
+                method: str = "hpcp", ksplit: int = 0):
     """Bounds for one GPU update from the master D (FP64) at coefficient c.
 
     Returns a dict with
@@ -148,7 +154,7 @@ def step_bounds(D: np.ndarray, c: float, precision: str, fold_every: int = 0,
     off = ~np.eye(M, dtype=bool)
     X2 = D @ D
     # K1: X2 = D D, then encoded (off-diagonal); diagonal from FP64 row sums
-    dP1, P1 = product_bound(D, D, M, precision, fold_every)
+    dP1, P1 = product_bound(D, D, M, precision, fold_every, ksplit)
     rowsq = (D * D).sum(1)
     E1 = np.where(off, dP1 + u_enc * (np.abs(X2) + dP1) + a_enc, 0.0)
     E1[np.diag_indices(M)] = 2 * M * U64 * rowsq + 4 * M * U64 * np.diag(P1)
@@ -156,7 +162,7 @@ def step_bounds(D: np.ndarray, c: float, precision: str, fold_every: int = 0,
     E1 = E1 + 2 * M * U64 * P1
     X2m = X2   # master of X2 to first order
     # K2: X3 = X2 D (product of the masters)
-    dP2, P2 = product_bound(X2m, D, M, precision, fold_every)
+    dP2, P2 = product_bound(X2m, D, M, precision, fold_every, ksplit)
     if method == "hpcp":
         a, b, e = 1 - 2 * c, 2 + 2 * c, -2.0
     elif c <= 0.5:
@@ -179,7 +185,7 @@ def step_bounds(D: np.ndarray, c: float, precision: str, fold_every: int = 0,
     T3_det = (E1 * A).sum() + 4 * M * U64 * (np.abs(X2) * A).sum()
     # statistical: Var E1_ij <= (2 u)^2 kappa P1^2 / 3 + (u_enc X2)^2 / 3 + u_drop^2 sum a^2 b^2 / 9;
     # each off-diagonal pair enters T3 twice with the same (mirrored) error
-    kappa = accumulation_kappa(M, precision, fold_every)
+    kappa = accumulation_kappa(M, precision, fold_every, ksplit)
     D2sq = D * D
     var = ((2 * u) ** 2 * kappa * (1.01 * P1) ** 2 / 3 + (u_enc * X2) ** 2 / 3
            + (u_drop ** 2 / 9) * (D2sq @ D2sq) + a_enc ** 2 / 3)

@@ -71,12 +71,12 @@ def gpu_iterates(w, precision, steps, **opts):
     return out, hist
 
 
-def check_step(Dn, Dn1, row, precision, fold_every=0, label=""):
+def check_step(Dn, Dn1, row, precision, fold_every=0, label="", ksplit=0):
     """One update: the GPU's D_{n+1} against the oracle's update of D_n at
     the GPU's c_n; T2, T3 and c_n against the oracle's traces of D_n."""
     n, t1, t2, t3, c = row[0], row[1], row[2], row[3], row[4]
     ref, (o1, o2, o3, oc) = oracle.update_at(Dn, c)
-    b = step_bounds(Dn, c, precision, fold_every)
+    b = step_bounds(Dn, c, precision, fold_every, ksplit=ksplit)
     diff = np.abs(Dn1 - ref)
     ratio = diff / b["dD"]
     k = np.unravel_index(int(np.argmax(ratio)), ratio.shape)
@@ -154,6 +154,18 @@ def test_fold_periods_element_wise(precision):
         it, hist = gpu_iterates(w, precision, [1], fold_every=fold)
         check_step(it[1], it[2], hist[1], precision, fold_every=fold,
                    label=f"{precision} fold={fold}")
+
+
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x6", "bf16"])
+def test_ksplit_element_wise(precision):
+    """Every tile pair split along K over 4 blocks whose FP32 totals meet in
+    FP64 (ksplit): each block accumulates a quarter of K, within the bound of
+    that scheme; M = 1000 has 10 pairs, so every block is a split."""
+    w = workloads.spectral(1000, 377, gap=0.1, seed=13)
+    it, hist = gpu_iterates(w, precision, [0, 1], ksplit=4)
+    for n in (0, 1):
+        check_step(it[n], it[n + 1], hist[n], precision, label=f"{precision} ksplit=4",
+                   ksplit=4)
 
 
 @pytest.fixture(scope="module")

@@ -312,6 +312,23 @@ def test_full_size_fold_against_one_accumulator(config3):
         log(f"  fp16x3 fold={fold}: iters={res.iters} err={errs[fold]:.3e}")
     assert errs[0] < errs[1000] / (3.7 / 2)
 
+
+def test_full_size_ksplit_combines_in_fp64(config3):
+    """M = 8192, FP16X3 with every pair split along K over 8 blocks whose
+    FP32 totals are added in FP64: each block folds its 32 of the 256 K
+    stages every 3 (sqrt(32 / 3)), about 3 x 3 + 32 / 3 = 20 roundings per
+    term against 3 x 9 + 256 / 9 = 56 for the whole-K fold, a factor
+    sqrt(56 / 20) = 1.7 in the accumulated rounding; with the encoding's own
+    share unchanged the error must still drop by at least 1.2."""
+    w, ref, _ = config3
+    D0, r0 = run_gpu(w, "fp16x3", tol_ddbar=1e-6)
+    D8, r8 = run_gpu(w, "fp16x3", tol_ddbar=1e-6, ksplit=8)
+    e0, e8 = rel_err(D0, ref), rel_err(D8, ref)
+    log(f"  fp16x3: err {e0:.3e} (whole K), {e8:.3e} (ksplit 8); iters {r0.iters}, {r8.iters}")
+    assert r8.status in gcp.SUCCESS and abs(r8.iters - r0.iters) <= 1
+    assert np.abs(r8.col("t1") - w.N).max() < 1e-10
+    assert e8 < e0 / 1.2
+
 # ------------------------------------------------------- precision schedule
 
 def _ctx_run(w, **opts):
