@@ -107,7 +107,11 @@ typedef struct {
                                precise encoding: a late FP64 phase makes the result
                                idempotent to FP64 level and lets it reach tolerances
                                below the early encoding's rounding floor. */
-    int32_t pad;
+    int32_t final_precision; /* a third phase: -1 (default) = none; otherwise the encoding
+                               of every product once |Tr(D Dbar)| <= final_ddbar (after
+                               late_precision's phase, or directly from the first one when
+                               late_precision is -1); final_ddbar <= switch_ddbar when
+                               both are given.  E.g. FP16X3 -> BF16X6 -> FP64. */
     double switch_ddbar;   /* see late_precision (default 0) */
     int32_t method;        /* GCP_METHOD_HPCP (default): eq. (hpcp3); GCP_METHOD_PMCP: the
                               Palser-Manolopoulos canonical purification of the
@@ -161,6 +165,7 @@ typedef struct {
                               Tr(D Dbar) or c outside [0,1] is a breakdown).  Within the floor a
                               stalled or negative Tr(D Dbar) stops the solve with
                               GCP_STOPPED_AT_FLOOR instead of GCP_ERR_BREAKDOWN. */
+    double final_ddbar;    /* see final_precision (default 0) */
 } gcp_options;
 
 enum { GCP_METHOD_HPCP = 0, GCP_METHOD_PMCP = 1 };

@@ -71,12 +71,13 @@ class Options(ctypes.Structure):
                 ("tol_ddbar", ctypes.c_double), ("tol_idem", ctypes.c_double),
                 ("fold_every", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("keep_iterates", ctypes.c_int32), ("bwd_precision", ctypes.c_int32),
-                ("late_precision", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("late_precision", ctypes.c_int32), ("final_precision", ctypes.c_int32),
                 ("switch_ddbar", ctypes.c_double), ("method", ctypes.c_int32),
                 ("init_mode", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("delta", ctypes.c_double), ("hole", ctypes.c_int32),
                 ("checkpoint_every", ctypes.c_int32), ("sync_every", ctypes.c_int32),
-                ("ksplit", ctypes.c_int32), ("floor_ddbar", ctypes.c_double)]
+                ("ksplit", ctypes.c_int32), ("floor_ddbar", ctypes.c_double),
+                ("final_ddbar", ctypes.c_double)]
 
 
 METHODS = {"hpcp": 0, "pmcp": 1}           # the recursion
@@ -189,7 +190,8 @@ class Context:
     def __init__(self, M: int, precision="fp64", max_iter: int = 100, tol_ddbar: float = 1e-6,
                  tol_idem: float = 0.0, fold_every: int = 0, profile: bool = False,
                  keep_iterates: bool = False, bwd_precision="fp64", late_precision=None,
-                 switch_ddbar: float = 0.0, method: str = "hpcp", init: str = "pmcp",
+                 switch_ddbar: float = 0.0, final_precision=None, final_ddbar: float = 0.0,
+                 method: str = "hpcp", init: str = "pmcp",
                  alpha: float = 0.5, delta: float = 2.0 / 3.0, hole: bool = False,
                  checkpoint_every: int = 0, sync_every: int = 4, ksplit: int = 0,
                  floor_ddbar: float = math.nan, stream=None):
@@ -208,6 +210,8 @@ class Context:
         o.bwd_precision = int(Precision.parse(bwd_precision))
         o.late_precision = -1 if late_precision is None else int(Precision.parse(late_precision))
         o.switch_ddbar = float(switch_ddbar)
+        o.final_precision = -1 if final_precision is None else int(Precision.parse(final_precision))
+        o.final_ddbar = float(final_ddbar)
         o.method = METHODS[method]
         o.init_mode = INITS[init]
         o.alpha = float(alpha)

@@ -90,7 +90,8 @@ struct gcp_ctx {
     int nfull = 0;    // 16-bit kernel: pairs computed whole ...
     int nsplit = 1;   // ... and K splits of each remaining pair
     double floor_ddbar = 0.0;   // rounding floor of |Tr(D Dbar)| (set by gcp_init)
-  } pc[2];
+    double enter_ddbar = 0.0;   // schedule: this encoding from |Tr(D Dbar)| <= enter_ddbar
+  } pc[3];                      // the phases of the precision schedule, in order
   int nprec = 1;
   void *Xc = nullptr;       // conversion target of a precision switch
   float *g16_ws = nullptr;  // K-split partial tiles (see k_gemm16)
@@ -121,7 +122,7 @@ struct gcp_ctx {
     int pi = 0;              // encoding index (precision schedule)
   };
   std::vector<Ckpt> ckpts;
-  int n_switch = -1;         // update at which the schedule switched encodings
+  int n_switch[3] = {-1, -1, -1};   // update at which the schedule entered phase k
   int bwd_p = -1;           // updates covered by the stored iterates (-1: none)
   void *bG[2] = {nullptr, nullptr};
   void *bX2 = nullptr, *bAT = nullptr, *bCT = nullptr;
@@ -242,6 +243,8 @@ extern "C" int gcp_options_default(gcp_options *opt) {
   opt->bwd_precision = GCP_FP64;
   opt->late_precision = -1;
   opt->switch_ddbar = 0.0;
+  opt->final_precision = -1;
+  opt->final_ddbar = 0.0;
   opt->method = GCP_METHOD_HPCP;
   opt->init_mode = GCP_INIT_PMCP;
   opt->alpha = 0.5;
@@ -273,8 +276,11 @@ static int check_options(const gcp_options &o, int64_t M, ErrText &err) {
     err = "gcp_create: keep_iterates must be 0 or 1 and bwd_precision FP64 or FP32";
     return GCP_ERR_INVALID_ARG;
   }
-  if (o.late_precision < -1 || o.late_precision > GCP_BF16X6 || !(o.switch_ddbar >= 0.0)) {
-    err = "gcp_create: late_precision must be -1 or a precision, switch_ddbar >= 0";
+  if (o.late_precision < -1 || o.late_precision > GCP_BF16X6 || !(o.switch_ddbar >= 0.0) ||
+      o.final_precision < -1 || o.final_precision > GCP_BF16X6 || !(o.final_ddbar >= 0.0) ||
+      (o.late_precision >= 0 && o.final_precision >= 0 && o.final_ddbar > o.switch_ddbar)) {
+    err = "gcp_create: late_precision and final_precision must be -1 or a precision, "
+          "switch_ddbar and final_ddbar >= 0, final_ddbar <= switch_ddbar";
     return GCP_ERR_INVALID_ARG;
   }
   if (o.sync_every < 1 || !(std::isnan(o.floor_ddbar) || o.floor_ddbar >= 0.0) ||
@@ -303,12 +309,18 @@ static void setup_ctx(gcp_ctx *c, int64_t M, const gcp_options &o, void *stream)
   c->opt = o;
   c->stream = (hipStream_t)stream;
   (void)hipGetDevice(&c->device);
+  // the schedule's phases: an encoding that repeats the previous one adds none
   c->pc[0].prec = o.precision;
+  c->pc[0].enter_ddbar = INFINITY;
   c->nprec = 1;
-  if (o.late_precision >= 0 && o.late_precision != o.precision) {
-    c->pc[1].prec = o.late_precision;
-    c->nprec = 2;
-  }
+  const int later[2] = {o.late_precision, o.final_precision};
+  const double enter[2] = {o.switch_ddbar, o.final_ddbar};
+  for (int q = 0; q < 2; ++q)
+    if (later[q] >= 0 && later[q] != c->pc[c->nprec - 1].prec) {
+      c->pc[c->nprec].prec = later[q];
+      c->pc[c->nprec].enter_ddbar = enter[q];
+      ++c->nprec;
+    }
   // tile partial sums: one per upper tile (FP64/FP32 kernel) or two per
   // tile pair (16-bit kernel, zero for the half of a pair below the diagonal)
   c->ntpart = 0;
@@ -445,7 +457,7 @@ extern "C" const char *gcp_last_error(const gcp_ctx *c) {
 static int reduce(gcp_ctx *c, const double *part, int nslots, int mode, double *out,
                   const double *extra, const double *tpart, int ntp, int iter,
                   bool skip_if_stopped = false, double floor_ddbar = 0.0,
-                  bool early_stop = false) {
+                  bool early_stop = false, bool recheck = false) {
   RedArgs a{};
   a.part = part;
   a.nslots = nslots;
@@ -465,6 +477,7 @@ static int reduce(gcp_ctx *c, const double *part, int nslots, int mode, double *
   a.floor_ddbar = floor_ddbar;
   a.skip_if_stopped = skip_if_stopped ? 1 : 0;
   a.early_stop = early_stop ? 1 : 0;
+  a.recheck = recheck ? 1 : 0;
   a.sc = c->sc;
   a.hist = c->hist;
   HIPCHK(c, launch_reduce(a, c->stream));
@@ -715,6 +728,8 @@ static int store_iterate(gcp_ctx *c, int n, int k, int prec) {
 struct LaunchLog {
   bool prof = false;
   int n = 0;
+  int phase[3] = {0, 0, 0};   // launches in each phase of the schedule
+  int reruns = 0;             // second K1 of an update after a change of encoding
 };
 
 // One product launch in encoding pc[pi].
@@ -727,12 +742,17 @@ static int run_product(gcp_ctx *c, GemmArgs &g, int pi, LaunchLog *log) {
   if (ev) HIPCHK(c, hipEventRecord(c->events[2 * log->n], c->stream));
   HIPCHK(c, launch_gemm(q.prec, g, c->stream));
   if (ev) HIPCHK(c, hipEventRecord(c->events[2 * log->n + 1], c->stream));
-  if (log) ++log->n;
+  if (log) {
+    ++log->n;
+    ++log->phase[pi];
+  }
   return GCP_OK;
 }
 
 // K1 of update n on the iterate in buffer k: X2 = D D and the scalar step.
-static int step_k1(gcp_ctx *c, GemmArgs &g, int pi, int k, int n, LaunchLog *log) {
+// recheck: the same iterate once more, in a new encoding (after a switch).
+static int step_k1(gcp_ctx *c, GemmArgs &g, int pi, int k, int n, LaunchLog *log,
+                   bool recheck = false) {
   g.mode = 0;
   g.A = c->Dp[k];
   g.B = c->Dp[k];
@@ -743,7 +763,7 @@ static int step_k1(gcp_ctx *c, GemmArgs &g, int pi, int k, int n, LaunchLog *log
   int st = run_product(c, g, pi, log);
   if (st != GCP_OK) return st;
   return reduce(c, c->part, c->nt, 1, c->d3, nullptr, c->tpart, c->pc[pi].ntpart, n,
-                g.status != nullptr, c->pc[pi].floor_ddbar);
+                g.status != nullptr, c->pc[pi].floor_ddbar, false, recheck);
 }
 
 // K2 of update n: D_{n+1} into buffer 1 - k.
@@ -764,15 +784,17 @@ static int step_k2(gcp_ctx *c, GemmArgs &g, int pi, int k, int n, LaunchLog *log
                 solve, c->pc[pi].floor_ddbar, solve && !(c->opt.tol_idem > 0.0));
 }
 
-// Precision schedule: re-encode D_n (buffer k) and X2 = D_n^2 in pc[1]; the
-// FP64 diagonals (dg, d2, d3) and c_n are unchanged, the residuals of the new
-// encoding replace rD and s2.
-static int switch_precision(gcp_ctx *c, int k) {
-  const int pa = c->pc[0].prec, pb = c->pc[1].prec;
+// Precision schedule: re-encode D_n (buffer k) from phase `from` into phase
+// `to`'s encoding, the FP64 diagonal kept and the new encoding's residual in
+// rD.  D_n^2 is then formed again, in the new encoding, by a second K1 of
+// the same update (recheck): c_n and the next iterate then carry none of the
+// old encoding's rounding of D^2 (with it, the first update of a precise
+// phase inherits the old encoding's noise in Tr(D Dbar), which can be
+// negative far above the new encoding's rounding floor).
+static int switch_precision(gcp_ctx *c, int k, int from, int to) {
+  const int pa = c->pc[from].prec, pb = c->pc[to].prec;
   HIPCHK(c, launch_convert(pa, pb, c->Dp[k], c->dg[k], c->Xc, c->rD[k], c->Mp, c->stream));
   std::swap(c->Dp[k], c->Xc);
-  HIPCHK(c, launch_convert(pa, pb, c->X2p, c->d2[k], c->Xc, c->s2, c->Mp, c->stream));
-  std::swap(c->X2p, c->Xc);
   return GCP_OK;
 }
 
@@ -824,10 +846,14 @@ static int recompute_segment(gcp_ctx *c, int n0, int n1) {
   for (int n = n0; n < n1; ++n) {
     int st = step_k1(c, g, pi, k, n, nullptr);
     if (st != GCP_OK) return st;
-    if (n == c->n_switch) {
-      st = switch_precision(c, k);
+    int to = pi;
+    while (to + 1 < c->nprec && n == c->n_switch[to + 1]) ++to;
+    if (to != pi) {
+      st = switch_precision(c, k, pi, to);
       if (st != GCP_OK) return st;
-      pi = 1;
+      pi = to;
+      st = step_k1(c, g, pi, k, n, nullptr, true);
+      if (st != GCP_OK) return st;
     }
     st = store_iterate(c, n - n0, k, c->pc[pi].prec);
     if (st != GCP_OK) return st;
@@ -891,7 +917,7 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
   setup_gemm(c, g, 0);
   g.status = &c->sc->status;   // launches past the device's stop do nothing
   const int ck = keep && c->opt.checkpoint_every >= 2 ? c->opt.checkpoint_every : 0;
-  c->n_switch = -1;
+  for (int q = 0; q < 3; ++q) c->n_switch[q] = -1;
 
   // Update n reads D_n from buffer n % 2 and writes D_{n+1} to the other.
   // The decision to stop is taken on the device (k_reduce, before c_n is
@@ -900,7 +926,7 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
   // host checks after every D^2, because the switch is decided there.
   int status = 0, n = 0, syncs = 0;
   for (;;) {
-    const bool per_step = c->nprec > 1 && pi == 0;
+    const bool per_step = pi + 1 < c->nprec;
     const int nb = per_step ? 1 : c->opt.sync_every;
     bool stopped = false;
     for (int q = 0; q < nb && n <= max_iter; ++q, ++n) {
@@ -920,12 +946,28 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
           stopped = true;
           break;
         }
-        if (std::fabs(c->sc_host->t1 - c->sc_host->t2) <= c->opt.switch_ddbar) {
-          st = switch_precision(c, k);
+        int to = pi;
+        while (to + 1 < c->nprec &&
+               std::fabs(c->sc_host->t1 - c->sc_host->t2) <= c->pc[to + 1].enter_ddbar) {
+          ++to;
+          c->n_switch[to] = n;
+        }
+        if (to != pi) {
+          st = switch_precision(c, k, pi, to);
           if (st != GCP_OK) return st;
-          pi = 1;
-          prec = c->pc[1].prec;
-          c->n_switch = n;
+          pi = to;
+          prec = c->pc[pi].prec;
+          st = step_k1(c, g, pi, k, n, &lg, true);
+          if (st != GCP_OK) return st;
+          ++lg.reruns;
+          HIPCHK(c, hipMemcpyAsync(c->sc_host, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost,
+                                   c->stream));
+          HIPCHK(c, hipStreamSynchronize(c->stream));
+          ++syncs;
+          if (c->sc_host->status != 0) {
+            stopped = true;
+            break;
+          }
         }
       }
       // the iterate K2 reads, in the encoding it reads it (after a switch)
@@ -980,9 +1022,10 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
   if (status == 3) rc = GCP_ERR_BREAKDOWN;
   if (status == 4) rc = GCP_STOPPED_AT_FLOOR;
   // launches that did work: K1 of updates 0..p (0..p-1 when the stop was
-  // decided from the traces of D_p) and K2 of 0..p-1 (any after them were
-  // enqueued past the stop and returned at once)
-  const int worked = 2 * iters + (c->sc_host->on_traces ? 0 : 1);
+  // decided from the traces of D_p), K2 of 0..p-1 and the second K1 after
+  // each change of encoding (any after them were enqueued past the stop and
+  // returned at once; they all fall in the last phase)
+  const int worked = 2 * iters + (c->sc_host->on_traces ? 0 : 1) + lg.reruns;
   const int real = worked < lg.n ? worked : lg.n;
   if (res) {
     std::memset(res, 0, sizeof(*res));
@@ -1002,12 +1045,15 @@ extern "C" int gcp_purify(gcp_ctx *c, void *D, int32_t dtype, int64_t ldd, gcp_r
     const double Md = (double)c->M;
     res->gemm_flops = (double)real * Md * Md * (Md + 1.0);
     // issued MFMA flops: whole 128 x 128 tiles of the padded size times the
-    // split products; launches 0 .. 2 n_switch are in the first encoding
+    // split products, launch by launch in each phase's encoding
     const double tile_fl = (double)c->ntiles * 2.0 * 128.0 * 128.0 * (double)c->Mp;
-    const int n0 = c->n_switch >= 0 ? 2 * c->n_switch + 1 : real;
-    const int first = n0 < real ? n0 : real;
-    res->mfma_flops = tile_fl * ((double)first * products(c->pc[0].prec) +
-                                 (double)(real - first) * products(c->pc[c->nprec - 1].prec));
+    double mf = 0.0;
+    for (int q = 0; q < c->nprec; ++q) {
+      int nq = lg.phase[q];
+      if (q == pi) nq -= lg.n - real;   // the void launches past the stop
+      mf += (double)nq * products(c->pc[q].prec);
+    }
+    res->mfma_flops = tile_fl * mf;
     double ms = 0.0;
     if (prof) {
       for (int k = 0; k < real; ++k) {

@@ -132,7 +132,8 @@ struct RedArgs {
   double tol_ddbar, tol_idem, N;
   double floor_ddbar;  // rounding floor of |Tr(D Dbar)| of the encoding
   int skip_if_stopped; // 1: do nothing once sc->status is non-zero
-  int pad2;
+  int recheck;         // mode 1: the same iterate again (after a change of encoding):
+                       // no stall test against, and no update of, prev_ddbar
   Scalars *sc;
   double *hist;
 };

@@ -1021,11 +1021,11 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
       // is rounding noise and stops decreasing: the iterate is then as
       // idempotent as the encoding allows and the solve stops there.
       const bool bad = !(ddbar > 0.0) || !isfinite(c) || c < 0.0 || c > 1.0;
-      const bool stalled = fabs(ddbar) >= sc->prev_ddbar;
+      const bool stalled = !a.recheck && fabs(ddbar) >= sc->prev_ddbar;
       if ((bad || stalled) && fabs(ddbar) <= a.floor_ddbar) status = 4;
       else if (bad) status = 3;
     }
-    sc->prev_ddbar = fabs(ddbar);
+    if (!a.recheck) sc->prev_ddbar = fabs(ddbar);
     if (status != 0) sc->iter = a.iter;
     sc->t3 = t3;
     sc->omega = om;

@@ -43,12 +43,13 @@ def test_struct_layout_matches_c_compiler(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "gcp.h"\n'
-        'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gcp_options),'
+        'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(gcp_options),'
         ' sizeof(gcp_verify_result), offsetof(gcp_verify_result, ms),'
         ' sizeof(gcp_result), offsetof(gcp_options, fold_every),'
         ' offsetof(gcp_options, checkpoint_every), offsetof(gcp_result, gemm_launches),'
         ' offsetof(gcp_result, mfma_flops), offsetof(gcp_options, floor_ddbar),'
-        ' offsetof(gcp_result, host_syncs), offsetof(gcp_options, ksplit));return 0;}\n')
+        ' offsetof(gcp_result, host_syncs), offsetof(gcp_options, ksplit),'
+        ' offsetof(gcp_options, final_ddbar), offsetof(gcp_options, final_precision));return 0;}\n')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
@@ -57,7 +58,8 @@ def test_struct_layout_matches_c_compiler(tmp_path):
                    gcp.Options.fold_every.offset, gcp.Options.checkpoint_every.offset,
                    gcp.CResult.gemm_launches.offset, gcp.CResult.mfma_flops.offset,
                    gcp.Options.floor_ddbar.offset, gcp.CResult.host_syncs.offset,
-                   gcp.Options.ksplit.offset]
+                   gcp.Options.ksplit.offset, gcp.Options.final_ddbar.offset,
+                   gcp.Options.final_precision.offset]
 
 
 def test_options_default(lib):
@@ -68,6 +70,7 @@ def test_options_default(lib):
             o.init_mode, o.alpha, o.delta, o.hole, o.checkpoint_every, o.sync_every, o.ksplit) == \
         (0, 100, 1e-6, 0.0, 0, 0, 0, 0, -1, 0.0, 0, 0, 0.5, 2.0 / 3.0, 0, 0, 4, 0)
     assert math.isnan(o.floor_ddbar)
+    assert (o.final_precision, o.final_ddbar) == (-1, 0.0)
     assert lib.gcp_options_default(None) == gcp.ERR_INVALID_ARG
 
 
@@ -94,11 +97,17 @@ def test_create_rejects_bad_arguments_before_touching_the_device(lib):
         setattr(o, field, bad)
         assert lib.gcp_create(ctypes.byref(h), 16, ctypes.byref(o), None) == gcp.ERR_INVALID_ARG
         assert b"init_mode" in lib.gcp_last_error(None)
-    for field, bad in (("late_precision", 7), ("late_precision", -2), ("switch_ddbar", -1.0)):
+    for field, bad in (("late_precision", 7), ("late_precision", -2), ("switch_ddbar", -1.0),
+                       ("final_precision", 7), ("final_ddbar", -1.0)):
         o = gcp.default_options()
         setattr(o, field, bad)
         assert lib.gcp_create(ctypes.byref(h), 16, ctypes.byref(o), None) == gcp.ERR_INVALID_ARG
         assert b"late_precision" in lib.gcp_last_error(None)
+    # the final phase's threshold lies below the late phase's
+    o = gcp.default_options()
+    o.late_precision, o.switch_ddbar = int(gcp.Precision.FP16X3), 1e-3
+    o.final_precision, o.final_ddbar = int(gcp.Precision.FP64), 1e-2
+    assert lib.gcp_create(ctypes.byref(h), 16, ctypes.byref(o), None) == gcp.ERR_INVALID_ARG
     for field, bad in (("sync_every", 0), ("floor_ddbar", -1.0), ("ksplit", -1), ("ksplit", 65)):
         o = gcp.default_options()
         setattr(o, field, bad)

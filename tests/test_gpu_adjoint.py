@@ -329,13 +329,17 @@ def test_adjoint_through_a_precision_switch():
                                    "switch_ddbar": 1e-2, "tol_ddbar": 1e-9},
                                   {"precision": "fp64", "late_precision": "fp16x3",
                                    "switch_ddbar": 1e30, "tol_ddbar": 1e-6},
+                                  {"precision": "fp16x3", "late_precision": "bf16x6",
+                                   "switch_ddbar": 1e-1, "final_precision": "fp64",
+                                   "final_ddbar": 1e-3, "tol_ddbar": 1e-9},
                                   {"hole": True}, {"max_iter": 0}])
 def test_checkpointed_backward_is_bitwise_the_kept_one(opts):
     """checkpoint_every = 3 and 5: every segment is recomputed from its
     checkpoint with the forward's kernels, so the gradient is bitwise the one
     from kept iterates (including a precision switch inside a segment, one at
     the first update, where the kept D_0 must be the re-encoded one that K2
-    reads, the hole recursion and a run with no update)."""
+    reads, a three-phase schedule, the hole recursion and a run with no
+    update)."""
     w = workloads.spectral(384, 150, 0.1, 35)
     Gp = workloads.sym_gaussian(384, 235)
     o = {"tol_ddbar": 1e-6}

@@ -41,20 +41,21 @@ def solve(w, **opts):
 
 # (workload, options, whether the stop needs the square of the last iterate:
 # the idempotency test and max_iter are decided after it, a stop on
-# Tr(D Dbar) from the last update's traces)
+# Tr(D Dbar) from the last update's traces; switches of encoding, each of
+# which forms D^2 once more)
 @pytest.mark.parametrize("case", [
-    ("chain", {"precision": "fp64", "tol_ddbar": 0.0, "tol_idem": 1e-10}, True),
-    ("spectral", {"precision": "fp16x3", "tol_ddbar": 1e-6}, False),
-    ("spectral", {"precision": "fp32", "tol_ddbar": 1e-6, "max_iter": 7}, True),
+    ("chain", {"precision": "fp64", "tol_ddbar": 0.0, "tol_idem": 1e-10}, True, 0),
+    ("spectral", {"precision": "fp16x3", "tol_ddbar": 1e-6}, False, 0),
+    ("spectral", {"precision": "fp32", "tol_ddbar": 1e-6, "max_iter": 7}, True, 0),
     ("spectral", {"precision": "fp16x3", "late_precision": "fp64", "switch_ddbar": 1e-2,
-                  "tol_ddbar": 1e-10}, False),
+                  "tol_ddbar": 1e-10}, False, 1),
 ])
 def test_sync_every_changes_nothing_but_the_host_syncs(case):
-    kind, opts, last_square = case
+    kind, opts, last_square, switches = case
     w = workloads.config(1) if kind == "chain" else workloads.spectral(520, 200, 0.1, 61)
     D1, r1 = solve(w, sync_every=1, profile=True, **opts)
     p = r1.iters
-    launches = 2 * p + (1 if last_square else 0)
+    launches = 2 * p + (1 if last_square else 0) + switches
     assert r1.gemm_launches == launches
     assert math.isnan(r1.idem) != last_square
     for k in (2, 3, 4, 7, 50):

@@ -361,6 +361,7 @@ def test_schedule_from_the_start_matches_the_late_precision_run():
 
 
 @pytest.mark.parametrize("early,late,switch,err_lo,err_hi", [("fp16x3", "fp64", 1e-3, 0.0, 1e-6),
+                                                             ("bf16x6", "fp64", 1e-3, 0.0, 1e-6),
                                                              ("bf16", "fp16x3", 1e-1, 1e-4, 3e-2)])
 def test_schedule_switch(early, late, switch, err_lo, err_hi):
     """Trace exact through the switch, convergence below the early encoding's
@@ -381,6 +382,68 @@ def test_schedule_switch(early, late, switch, err_lo, err_hi):
     assert err_lo <= err < err_hi
     if late == "fp64":
         assert idem < 1e-9
+
+
+def test_three_phase_schedule_never_entering_the_last_is_the_two_phase_run():
+    w = workloads.spectral(384, 150, 0.1, 53)
+    D2, r2 = _ctx_run(w, precision="fp16x3", late_precision="bf16x6", switch_ddbar=1e-2,
+                      tol_ddbar=1e-6)
+    D3, r3 = _ctx_run(w, precision="fp16x3", late_precision="bf16x6", switch_ddbar=1e-2,
+                      final_precision="fp64", final_ddbar=0.0, tol_ddbar=1e-6)
+    assert r3.iters == r2.iters and np.array_equal(D3, D2)
+    assert np.array_equal(r3.history, r2.history, equal_nan=True)
+    assert r3.mfma_flops == r2.mfma_flops
+
+
+@pytest.mark.parametrize("phases,err_lo,err_hi", [
+    (("bf16", 1e-1, "fp16x3", 1e-3, "fp64"), 1e-4, 3e-2),
+    (("fp16x3", 1e-1, "bf16x6", 1e-3, "fp64"), 0.0, 1e-6),
+    (("bf16x6", 1e-1, "fp32", 1e-3, "fp64"), 0.0, 1e-6),
+])
+def test_three_phase_schedule(phases, err_lo, err_hi):
+    """Three encodings entered at two thresholds of Tr(D Dbar): the trace
+    stays exact through both switches, the final FP64 phase makes D
+    idempotent to FP64 level and reaches a tolerance far below the earlier
+    encodings' floors, and the error is the earliest phase's (rounding in
+    the occupied-virtual block is not undone).  The issued MFMA flops count
+    each phase's launches with its own number of products.  At each switch
+    D^2 is formed again in the new encoding, so that the first update of a
+    precise phase carries none of the earlier encoding's rounding of D^2
+    (BF16X6 -> FP64 at 1e-3 broke down without it: the first FP64 update's
+    Tr(D Dbar) came out at -5e-8, BF16X6 noise far above FP64's floor)."""
+    early, sw1, late, sw2, final = phases
+    M, N = 520, 200
+    w = workloads.spectral(M, N, 0.1, 52)
+    ref = oracle.projector_from_spectrum(w.Q, w.lam, w.N)
+    D, res = _ctx_run(w, precision=early, late_precision=late, switch_ddbar=sw1,
+                      final_precision=final, final_ddbar=sw2, tol_ddbar=1e-11, max_iter=60)
+    err = rel_err(D, ref)
+    idem = float(np.linalg.norm(D @ D - D))
+    ddbar = res.col("t1") - res.col("t2")
+    # updates in each phase: the switch follows the D^2 whose Tr(D Dbar) is
+    # within the threshold, so update n runs its K2 in the new encoding
+    n1 = int(np.argmax(np.abs(ddbar) <= sw1))
+    n2 = int(np.argmax(np.abs(ddbar) <= sw2))
+    log(f"  {early}->{late}->{final}: iters={res.iters} switches at {n1}, {n2} err={err:.3e} "
+        f"idem={idem:.2e}")
+    assert res.status in gcp.SUCCESS
+    assert 0 < n1 <= n2 < res.iters
+    assert np.abs(res.col("t1") - w.N).max() < 1e-10
+    assert err_lo <= err < err_hi
+    assert idem < 1e-9
+    # first phase: K1 of updates 0..n1 and K2 of 0..n1-1; at a switch D^2 is
+    # formed again in the new encoding (a second K1 of the same update), so
+    # the second phase has K1 (again) and K2 of n1..n2-1 and K1 of n2
+    tile = (w.M + 255) // 256 * 256
+    nt = tile // 128
+    tile_fl = nt * (nt + 1) / 2 * 2.0 * 128 * 128 * tile
+    prods = {"bf16": 1, "fp16x3": 3, "bf16x6": 6, "fp64": 1, "fp32": 1}
+    launches = res.gemm_launches
+    a = 2 * n1 + 1
+    b = 2 * (n2 - n1) + 1 if n2 > n1 else 0
+    assert launches == 2 * res.iters + (2 if n2 > n1 else 1)
+    expect = tile_fl * (a * prods[early] + b * prods[late] + (launches - a - b) * prods[final])
+    assert res.mfma_flops == pytest.approx(expect, rel=1e-12)
 
 
 @pytest.mark.parametrize("precision,tol_ddbar,err_tol", [("fp64", 1e-9, 1e-10),
