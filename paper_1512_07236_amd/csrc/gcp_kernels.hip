@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "gcp_encode.h"
 #include "gcp_kernels.h"
 #include "gcp_mma.h"
@@ -189,14 +191,17 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
 // Pairs of horizontally adjacent 128 x 128 tiles, (ti, 2c) and (ti, 2c+1),
 // share one row panel of the left operand: a 128 x 256 output per block of
 // 8 waves (2 per SIMD), each wave 64 rows x 64 columns of one tile (4 x 4
-// MFMA blocks).  The panels stream through a 3-stage LDS ring, one K stage
-// of 32 per step.  All split products of a K step go into one FP32 chunk
-// accumulator, which is added
-// into a running FP32 total every `fold` K steps.  With r products per step
-// and n = K/32 steps the rounding error then grows like sqrt(r*fold + n/fold)
-// instead of sqrt(r*n): fold = sqrt(n/r) (the default) minimises it.  This
-// accumulation error, not the operand encoding, bounds the accuracy of the
-// split encodings at large M.
+// MFMA blocks).  The panels stream through a 3-stage LDS ring (2 stages for
+// three planes), one K stage of 32 per step.  All split products of a K step
+// go into one FP32 chunk accumulator, which is added into a running FP32
+// total every `fold` K steps.  With r products per step and n = K/32 steps
+// the rounding error then grows like sqrt(r*fold + n/fold) instead of
+// sqrt(r*n): fold = sqrt(n/r) (the default) minimises it.  This accumulation
+// error, not the operand encoding, bounds the accuracy of the split
+// encodings at large M.  A pair may be split along K over several blocks
+// (the pairs of a last partial round, or every pair with the ksplit option):
+// each split folds its own K range, and the last to finish adds the splits'
+// FP32 totals in FP64, in split order.
 constexpr int PAIR_COLS = 2;
 
 // Pair (ti, c) of block b, c >= ti/2, in column-major order of the pair
@@ -554,8 +559,14 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
   double rsum[8], csum[8], tsum = 0.0;
 #pragma unroll
   for (int r = 0; r < 8; ++r) rsum[r] = csum[r] = 0.0;
-  if (tvalid && !(dtile && br > bc)) {   // blocks below the diagonal are mirrors
-    const bool dblk = dtile && br == bc;
+  // The 8 x 8 blocks on a tile's diagonal hold the diagonal elements, formed
+  // from the FP64 side vectors, and are their own mirrors.  DK = 1 compiles
+  // such a block, DK = 0 every other block (the lean path), DK = 2 decides at
+  // run time.  Both update modes are compiled separately.
+  auto element_block = [&](auto dk_t, auto mode_t) {
+    constexpr int DK = decltype(dk_t)::value;
+    constexpr int MODE = decltype(mode_t)::value;
+    const bool dblk = DK == 1 || (DK == 2 && dtile && br == bc);
     const int64_t j0 = (int64_t)tjj * TILE + bc * 8;
     // Encoded results, row r of the block, 8 halves per plane, kept for the
     // mirrored store.  Planes p < NPARK are parked in this thread's own 8 x 8
@@ -571,7 +582,7 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
         dv[p] = *(const v4u *)(Bg + eoff<P>(i, j0, p, Mp));
-        if (g.mode == 1) xv[p] = *(const v4u *)(Ag + eoff<P>(i, j0, p, Mp));
+        if constexpr (MODE == 1) xv[p] = *(const v4u *)(Ag + eoff<P>(i, j0, p, Mp));
       }
       const float *vr = V + (th * TILE + br * 8 + r) * EPLD + bc * 8;
       uint16_t o[NP][8];
@@ -583,9 +594,9 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
         for (int p = 0; p < NP; ++p) dp[p] = (uint16_t)(dv[p][e >> 1] >> (16 * (e & 1)));
         const double v = (double)vr[e] * S;
         double prod, diff;
-        if (g.mode == 0) {
+        if constexpr (MODE == 0) {
           double Dm, x2;
-          if (i == j) {
+          if (DK != 0 && i == j) {
             Dm = vrow[2 * TILE + br * 8 + r];
             x2 = vrow[3 * TILE + br * 8 + r];
           } else {
@@ -593,13 +604,13 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
             x2 = v + Dm * (vrow[br * 8 + r] + vcol[th * TILE + bc * 8 + e]);
           }
           E::enc(x2, op);
-          const double x2m = (i == j) ? x2 : E::dec(op);
-          if (i == j) g.s2[i] = x2 - E::dec(op);
+          const double x2m = (DK != 0 && i == j) ? x2 : E::dec(op);
+          if (DK != 0 && i == j) g.s2[i] = x2 - E::dec(op);
           prod = x2m * Dm;
           diff = x2m - Dm;
         } else {
           double Dm, dn;
-          if (i == j) {
+          if (DK != 0 && i == j) {
             Dm = vrow[2 * TILE + br * 8 + r];
             dn = a_coef * Dm + b_coef * vrow[3 * TILE + br * 8 + r] + e_coef * vrow[4 * TILE + br * 8 + r];
           } else {
@@ -612,8 +623,8 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
             dn = a_coef * Dm + b_coef * X2m + e_coef * x3;
           }
           E::enc(dn, op);
-          const double dnm = (i == j) ? dn : E::dec(op);
-          if (i == j) {
+          const double dnm = (DK != 0 && i == j) ? dn : E::dec(op);
+          if (DK != 0 && i == j) {
             g.dg_new[i] = dn;
             g.rD_new[i] = dn - E::dec(op);
           }
@@ -624,7 +635,7 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
         for (int p = 0; p < NP; ++p) o[p][e] = op[p];
         if (dblk && i > j) continue;   // lower half of a diagonal block
         rsum[r] += prod;
-        if (i != j) {
+        if (DK == 0 || i != j) {
           csum[e] += prod;
           tsum += 2.0 * diff * diff;
         } else {
@@ -679,6 +690,23 @@ __global__ __launch_bounds__(NTH16, 1) void k_gemm16(GemmArgs g) {
                   (uint16_t)((obp[r][e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
         }
       }
+    }
+  };
+  if (tvalid && !(dtile && br > bc)) {   // blocks below the diagonal are mirrors
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    // (three planes: one body for both kinds of block; the split one measured
+    // slower there, its main loop scheduled worse)
+    if constexpr (NP == 3) {
+      if (g.mode == 0) element_block(I2{}, I0{});
+      else element_block(I2{}, I1{});
+    } else if (dtile && br == bc) {
+      if (g.mode == 0) element_block(I1{}, I0{});
+      else element_block(I1{}, I1{});
+    } else {
+      if (g.mode == 0) element_block(I0{}, I0{});
+      else element_block(I0{}, I1{});
     }
   }
   // row sums: the 16 threads of a block row (lanes differing in bits 0..3)
