@@ -294,7 +294,7 @@ def verify_quantities(D: np.ndarray, H: np.ndarray) -> dict:
 def scalar_map(eps: np.ndarray, N: int, emin: float, emax: float, mu: Optional[float] = None,
                tol_ddbar: float = 1e-6, tol_idem: float = 0.0, max_iter: int = 100,
                method: str = "hpcp", init: str = "pmcp", alpha: float = 0.5,
-               delta: float = 2.0 / 3.0):
+               delta: float = 2.0 / 3.0, c_given=None):
     """The recursion on eigenvalues (H with known spectrum eps).
 
     Every iterate is a polynomial in H, so D_n has the eigenvectors of H and
@@ -308,6 +308,11 @@ def scalar_map(eps: np.ndarray, N: int, emin: float, emax: float, mu: Optional[f
     alpha of the search of eq. (hpcpguessalpha), on eigenvalues (the same
     readings as the C oracle, including the fall-back to the PMCP guess when
     c_0 is outside [0, 1]).
+
+    c_given: update n applies c_given[n] (while there is one) instead of the c
+    of the iterate, which is still what the "c" column records: the map then
+    follows another solver's trajectory, whose c_n carry that solver's
+    rounding, and its traces differ from that solver's by trace rounding only.
     """
     eps = np.asarray(eps, dtype=np.float64)
     M = eps.size
@@ -374,6 +379,8 @@ def scalar_map(eps: np.ndarray, N: int, emin: float, emax: float, mu: Optional[f
         if not (0.0 <= c <= 1.0):
             status = BREAKDOWN
             break
+        if c_given is not None and n < len(c_given):
+            c = float(c_given[n])
         if method == "hpcp":
             x = x + 2.0 * (x * x * (1 - x) - c * x * (1 - x))
         elif c <= 0.5:

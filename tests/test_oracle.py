@@ -309,6 +309,31 @@ def test_scalar_map_reproduces_matrix_recursion():
     assert np.abs(r.D - Dmap).max() < 1e-10
 
 
+def test_scalar_map_with_given_c():
+    """c_given: the map's own c sequence gives the map itself, bitwise.  Any
+    other sequence moves T1 at every update by the trace of the correction of
+    eq. (hpcp3), 2[(T2 - T3) - c (T1 - T2)], which vanishes only for the
+    iterate's own c: the given c is the one applied."""
+    w = workloads.spectral(300, 100, 0.1, seed=8)
+    mu = np.trace(w.H) / w.M
+    s = oracle.scalar_map(w.lam, w.N, w.emin, w.emax, mu=mu, tol_ddbar=1e-9)
+    f = oracle.scalar_map(w.lam, w.N, w.emin, w.emax, mu=mu, tol_ddbar=1e-9, c_given=s["c"])
+    assert f["iters"] == s["iters"] and f["status"] == s["status"]
+    for k in ("t1", "t2", "t3", "c"):
+        assert np.array_equal(f[k], s[k])
+    cg = s["c"] + 1e-3
+    g = oracle.scalar_map(w.lam, w.N, w.emin, w.emax, mu=mu, tol_ddbar=0.0,
+                          max_iter=len(cg), c_given=cg)
+    n = g["iters"]
+    assert n >= 5
+    t1, t2, t3 = g["t1"][:n], g["t2"][:n], g["t3"][:n]
+    step = np.diff(g["t1"][:n + 1])
+    assert np.allclose(step, 2.0 * ((t2 - t3) - cg[:n] * (t1 - t2)), rtol=0, atol=1e-10)
+    assert np.abs(step).max() > 1e-4
+    # the recorded c is still the iterate's own
+    assert np.allclose(g["c"][:n], (t2 - t3) / (t1 - t2), rtol=0, atol=1e-12)
+
+
 # ------------------------------------------------------------- failure paths
 
 def test_degenerate_sizes():
