@@ -81,21 +81,21 @@ struct gcp_ctx {
   double *s2 = nullptr, *d3 = nullptr;
   double *part = nullptr, *tpart = nullptr, *bpart = nullptr;
   double *hvec = nullptr;   // 3 Mp scratch for H statistics
-  // launch configuration per encoding: [0] the main precision, [1] the late
-  // precision of a schedule (unused without one)
+  // launch configuration per encoding, one per phase of the schedule
   struct PrecCfg {
     int prec = GCP_FP64;
     int ntpart = 0;   // tile partial sums the reduction adds
-    int fold = 1;     // fold period of the 16-bit kernel (K stages)
-    int nfull = 0;    // 16-bit kernel: pairs computed whole ...
-    int nsplit = 1;   // ... and K splits of each remaining pair
+    int fold = 1;     // fold period of the product's accumulator (K stages)
+    int nfull = 0;    // product units (tile pairs, or tiles for FP64 / FP32) computed whole ...
+    int ntail = 0;    // ... and units split along K (0: none) ...
+    int nsplit = 1;   // ... over this many blocks each
     double floor_ddbar = 0.0;   // rounding floor of |Tr(D Dbar)| (set by gcp_init)
     double enter_ddbar = 0.0;   // schedule: this encoding from |Tr(D Dbar)| <= enter_ddbar
   } pc[3];                      // the phases of the precision schedule, in order
   int nprec = 1;
   void *Xc = nullptr;       // conversion target of a precision switch
-  float *g16_ws = nullptr;  // K-split partial tiles (see k_gemm16)
-  unsigned *g16_cnt = nullptr;
+  void *split_ws = nullptr;   // partial tiles of the K-split units
+  unsigned *split_cnt = nullptr;   // their arrival counters
   unsigned *counter = nullptr;
   Scalars *sc = nullptr;    // device
   Scalars *sc_host = nullptr;  // pinned
@@ -163,8 +163,8 @@ static void free_all(gcp_ctx *c) {
                   c->counter, c->sc, c->hist, c->D0p, c->dg0, c->rD0, c->d20};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
-  void *bptrs[] = {c->bG[0], c->bG[1], c->bX2, c->bAT, c->bCT, c->btpart, c->bvec, c->g16_ws,
-                   c->g16_cnt, c->vD, c->vH, c->vHD, c->vaux, c->Xc};
+  void *bptrs[] = {c->bG[0], c->bG[1], c->bX2, c->bAT, c->bCT, c->btpart, c->bvec, c->split_ws,
+                   c->split_cnt, c->vD, c->vH, c->vHD, c->vaux, c->Xc};
   for (void *p : bptrs)
     if (p) (void)hipFree(p);
   for (void *p : c->slots)
@@ -181,7 +181,7 @@ static void free_all(gcp_ctx *c) {
 }
 
 // Launch configuration of encoding pc[k].prec: tile partial count, fold
-// period and the K-split tail of the 16-bit kernel.
+// period and the K-split units of the product kernel.
 static void PrecCfgInit(gcp_ctx *c, int k) {
   gcp_ctx::PrecCfg &q = c->pc[k];
   const int prec = q.prec;
@@ -200,11 +200,43 @@ static void PrecCfgInit(gcp_ctx *c, int k) {
     f = prec == GCP_FP32 ? fp32_fold(c->Mp)
                          : (int)std::lround(std::sqrt((double)nk / ks / per_stage));
   q.fold = f < 1 ? 1 : f;
-  q.nfull = pair_count(c->nt);
   q.nsplit = 1;
-  if (elem_size(prec) != 2) return;
+  q.ntail = 0;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  if (elem_size(prec) != 2) {
+    // FP64 / FP32: tiles are equal units of work, two resident blocks per
+    // CU.  The tiles of a last partial round (all tiles when there are fewer
+    // than one round) would leave most slots idle, so each is split along K
+    // over up to 8 blocks of at least 64 (FP64) or 256 (FP32) K values.  At
+    // most 128 split blocks in all for M <= GCP_STATIC_MAX_M (16 MB of
+    // partial tiles, within the static workspace of gcp_purify_static), 512
+    // above.  Measured per product (FP64 / FP32): M = 1024 0.19 -> 0.13 /
+    // 0.11 -> 0.09 ms, M = 4096 1.69 -> 1.40 / 0.91 -> 0.70 ms, M = 8192
+    // 9.54 -> 9.53 / 5.03 -> 4.57 ms.
+    const int slots = 2 * cus;
+    const int nkt = (int)(c->Mp / (128 / elem_size(prec)));
+    const int tail = c->ntiles % slots;
+    const int cap = c->M <= GCP_STATIC_MAX_M ? 128 : 512;
+    int S = tail > 0 ? slots / tail : 1;
+    S = std::min(S, 8);
+    S = std::min(S, nkt / (prec == GCP_FP32 ? 8 : 4));
+    if (tail > 0 && tail * S > cap) S = cap / tail;
+    q.nfull = c->ntiles;
+    if (tail > 0 && S >= 2) {
+      q.nfull = c->ntiles - tail;
+      q.ntail = tail;
+      q.nsplit = S;
+    }
+    return;
+  }
+  const int npairs = pair_count(c->nt);
+  q.nfull = npairs;
   if (ks >= 2) {
     q.nfull = 0;
+    q.ntail = npairs;
     q.nsplit = ks;
     return;
   }
@@ -215,17 +247,13 @@ static void PrecCfgInit(gcp_ctx *c, int k) {
   // M = 8192 (32 tail pairs) 4 splits measured 2.06 ms per product against
   // 2.24 unsplit and 2.14 with 8 (each split re-pays the pipeline fill and
   // writes a 128 KB partial).
-  int cus = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
-      cus <= 0)
-    cus = 256;
-  const int npairs = pair_count(c->nt);
   const int tail = npairs % cus;
   int S = tail > 0 ? cus / tail : 1;
   if (S > nk / 8) S = nk / 8;
   if (S > 4) S = 4;
   if (tail > 0 && S >= 2) {
     q.nfull = npairs - tail;
+    q.ntail = tail;
     q.nsplit = S;
   }
 }
@@ -330,15 +358,15 @@ static void setup_ctx(gcp_ctx *c, int64_t M, const gcp_options &o, void *stream)
   }
 }
 
-// Tile pairs of the K-split tail of the 16-bit kernel (for any encoding of
-// the context) and the largest split count.
-static void split_tail(const gcp_ctx *c, int &tail, int &smax) {
+// K-split units of the product launches of any phase: the most units
+// (arrival counters) and the most split blocks (partial tiles of 128 KB).
+static void split_tail(const gcp_ctx *c, int &tail, int &blocks) {
   tail = 0;
-  smax = 1;
+  blocks = 0;
   for (int k = 0; k < c->nprec; ++k)
-    if (c->pc[k].nsplit > 1) {
-      tail = std::max(tail, pair_count(c->nt) - c->pc[k].nfull);
-      if (c->pc[k].nsplit > smax) smax = c->pc[k].nsplit;
+    if (c->pc[k].ntail > 0) {
+      tail = std::max(tail, c->pc[k].ntail);
+      blocks = std::max(blocks, c->pc[k].ntail * c->pc[k].nsplit);
     }
 }
 
@@ -374,12 +402,13 @@ static void for_each_buffer(gcp_ctx *c, bool one_shot, F &&f) {
   f((void **)&c->counter, sizeof(unsigned));
   f((void **)&c->sc, sizeof(Scalars));
   f((void **)&c->hist, (size_t)(c->opt.max_iter + 1) * GCP_HIST_COLS * sizeof(double));
-  int tail, smax;
-  split_tail(c, tail, smax);
+  int tail, blocks;
+  split_tail(c, tail, blocks);
   if (tail > 0) {
-    // one FP32 partial tile of 128 x 256 per split block
-    f((void **)&c->g16_ws, (size_t)tail * smax * 512 * 64 * sizeof(float));
-    f((void **)&c->g16_cnt, (size_t)tail * sizeof(unsigned));
+    // one partial tile of 128 KB per split block (FP32 128 x 256 of the
+    // 16-bit kernel, FP64 128 x 128 of the FP64 one)
+    f(&c->split_ws, (size_t)blocks * 128 * 1024);
+    f((void **)&c->split_cnt, (size_t)tail * sizeof(unsigned));
   }
   if (c->nprec > 1) f(&c->Xc, pb);
   if (!one_shot && c->opt.keep_iterates) {
@@ -426,10 +455,10 @@ extern "C" int gcp_create(gcp_ctx **out, int64_t M, const gcp_options *opt, void
     g_create_error = "gcp_create: device allocation failed";
     return GCP_ERR_NO_MEMORY;
   }
-  int ntail, smax;
-  split_tail(c, ntail, smax);
+  int ntail, nblk;
+  split_tail(c, ntail, nblk);
   const size_t vec = (size_t)c->Mp * sizeof(double);
-  if ((c->g16_cnt && hipMemsetAsync(c->g16_cnt, 0, (size_t)ntail * sizeof(unsigned),
+  if ((c->split_cnt && hipMemsetAsync(c->split_cnt, 0, (size_t)ntail * sizeof(unsigned),
                                      c->stream) != hipSuccess) ||
       hipMemsetAsync(c->counter, 0, sizeof(unsigned), c->stream) != hipSuccess ||
       hipMemsetAsync(c->s2, 0, vec, c->stream) != hipSuccess ||
@@ -537,8 +566,8 @@ static void setup_gemm(gcp_ctx *c, GemmArgs &g, int pi) {
   g.nfull = q.nfull;
   g.nsplit = q.nsplit;
   g.method = c->opt.method;
-  g.ws = c->g16_ws;
-  g.cnt = c->g16_cnt;
+  g.ws = c->split_ws;
+  g.cnt = c->split_cnt;
   g.part = c->part;
   g.tpart = c->tpart;
   g.s2 = c->s2;
@@ -1378,9 +1407,9 @@ extern "C" int gcp_purify_static(const double *H, int64_t ldh, int64_t M, int64_
   c.sc_host = &host_sc;
   // the array keeps the previous call's contents: the arrival counters and
   // the X2 diagonal residuals must start at zero
-  int ntail, smax;
-  split_tail(&c, ntail, smax);
-  if (launch_zero(c.g16_cnt, ntail, c.stream) != hipSuccess ||
+  int ntail, nblk;
+  split_tail(&c, ntail, nblk);
+  if (launch_zero(c.split_cnt, ntail, c.stream) != hipSuccess ||
       launch_zero(c.counter, 1, c.stream) != hipSuccess ||
       launch_zero(c.s2, 2 * c.Mp, c.stream) != hipSuccess) {
     g_create_error = "gcp_purify_static: clearing the workspace failed";

@@ -84,14 +84,16 @@ struct GemmArgs {
   int nt;              // Mp / 128
   int mode;            // 0: X2 = D D, 1: D_{n+1} = (1-2c) D + (2+2c) X2 - 2 X2 D
   int fold;            // fold period of the main accumulator, in K stages
-  // 16-bit kernel: blocks [0, nfull) compute whole pairs; the remaining pairs
-  // are each split over nsplit blocks along K (nsplit = 1: no split), whose
-  // FP32 partial tiles meet in ws and are added, in split order, by the
-  // last of them to finish (per-pair arrival counters in cnt, self-resetting)
+  // Blocks [0, nfull) compute whole units (tile pairs in the 16-bit kernel,
+  // tiles in the FP64 / FP32 one); the remaining units are each split over
+  // nsplit blocks along K (nsplit = 1: no split), whose partial tiles (FP32,
+  // or the accumulator type) meet in ws and are added in FP64, in split
+  // order, by the last of them to finish (per-unit arrival counters in cnt,
+  // self-resetting)
   int nfull;
   int nsplit;
   int method;          // 0 HPCP, 1 PMCP (update coefficients of mode 1)
-  float *ws;
+  void *ws;
   unsigned *cnt;
   const double *dg;    // diag(D) FP64
   const double *rD;    // diag(D) - dec(enc(diag(D)))

@@ -26,7 +26,11 @@
 namespace gcp {
 
 // FP64 / FP32 product kernel: one 128 x 128 upper-triangle tile per block of
-// 4 waves (2 x 2 grid of 64 x 64), MFMA 16x16x4, two blocks per CU.
+// 4 waves (2 x 2 grid of 64 x 64), MFMA 16x16x4, two blocks per CU.  Blocks
+// [0, nfull) compute whole tiles; each remaining tile is split along K over
+// nsplit blocks (the tiles of a last partial round, or every tile of a
+// product smaller than one round), whose partial tiles meet in ws and are
+// added in FP64, in split order, by the last of them to finish.
 template <int P>
 __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
   using E = Enc<P>;
@@ -37,8 +41,22 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) T smem[MmaCfg<P>::SMEM];
   if (g.status && *g.status != 0) return;   // the solve has stopped
 
-  int ti, tj, lin;
-  tile_of_block(blockIdx.x, g.nt, ti, tj, lin);
+  // whole tile, or split s of a tail tile over K stages [kb, ke)
+  const int nk_all = (int)(g.Mp / MmaCfg<P>::KT);
+  int ti, tj, lin, split = -1, kb = 0, ke = nk_all;
+  if ((int)blockIdx.x < g.nfull) {
+    tile_of_block(blockIdx.x, g.nfull, g.nt, ti, tj, lin);
+  } else {
+    // split-major: the blocks in flight together cover the same K range of
+    // consecutive tiles
+    const int u = (int)blockIdx.x - g.nfull;
+    const int ntail = ((int)gridDim.x - g.nfull) / g.nsplit;
+    split = u / ntail;
+    lin = g.nfull + u % ntail;
+    tile_of_index(lin, g.nt, ti, tj);
+    kb = split * nk_all / g.nsplit;
+    ke = (split + 1) * nk_all / g.nsplit;
+  }
   const int64_t Mp = g.Mp, PS = g.pstride;
   const int64_t arow0 = (int64_t)ti * TILE, brow0 = (int64_t)tj * TILE;
   const T *__restrict__ Ag = (const T *)g.A;
@@ -47,7 +65,44 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
   const int wm = wave >> 1, wn = wave & 1, l16 = lane & 15, lg = lane >> 4;
 
   Acc acc0[4][4];
-  mma_tile<P>(Ag, Bg, arow0, brow0, Mp, PS, smem, g.fold, acc0);
+  mma_tile<P>(Ag, Bg, arow0, brow0, Mp, PS, smem, g.fold, acc0, kb, ke);
+
+  if (split >= 0) {
+    // publish this split's partial tile; the last split to arrive adds all
+    // of them in split order (the sum does not depend on the arrival order)
+    // and runs the epilogue
+    const int t = lin - g.nfull;   // index among the split tiles
+    Acc *wsp = (Acc *)g.ws + ((int64_t)t * g.nsplit + split) * 16 * NTH;
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) wsp[(bi * 4 + bj) * NTH + tid] = acc0[bi][bj];
+    __threadfence();
+    unsigned *last = (unsigned *)smem;   // the stage buffers are free
+    __syncthreads();
+    if (tid == 0) *last = (atomicAdd(g.cnt + t, 1u) == (unsigned)g.nsplit - 1);
+    __syncthreads();
+    if (!*last) return;
+    __syncthreads();   // flag read by all before the epilogue reuses smem
+    __threadfence();
+    const Acc *w0 = (const Acc *)g.ws + (int64_t)t * g.nsplit * 16 * NTH;
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 4
+        for (int sp = 0; sp < g.nsplit; ++sp) {
+          const Acc v = w0[((int64_t)sp * 16 + bi * 4 + bj) * NTH + tid];
+          a0 += (double)v[0];
+          a1 += (double)v[1];
+          a2 += (double)v[2];
+          a3 += (double)v[3];
+        }
+        acc0[bi][bj] = Acc{(T)a0, (T)a1, (T)a2, (T)a3};
+      }
+    if (tid == 0) g.cnt[t] = 0u;   // ready for the next launch
+  }
 
   // ------------------------------------------------------------ epilogue
   const double S = E::PROD_SCALE;
@@ -1197,7 +1252,7 @@ static hipError_t launch_gemm_p(const GemmArgs &g, int ntiles, hipStream_t st) {
   if constexpr (Enc<P>::KIND >= 2)
     k_gemm16<P><<<gemm16_blocks(g), NTH16, 0, st>>>(g);
   else
-    k_gemm<P><<<ntiles, NTH, 0, st>>>(g);
+    k_gemm<P><<<g.nfull + (ntiles - g.nfull) * g.nsplit, NTH, 0, st>>>(g);
   return hipGetLastError();
 }
 

@@ -53,18 +53,12 @@ __device__ __forceinline__ v4f mfma16(v4u a, v4u b, v4f c) {
 
 __device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
 
-// Upper-triangle tile of block b.  Tiles are ordered in G x G groups of the
-// tile grid (the diagonal groups are triangular), row-major inside a group.
-// Blocks are dispatched round-robin over the 8 XCDs; each XCD gets a
-// contiguous run of that order, so the ~64 tiles resident on one XCD at a
-// time fall in one group and read about 2G row panels, which its L2 serves.
+// Upper-triangle tiles are ordered in G x G groups of the tile grid (the
+// diagonal groups are triangular), row-major inside a group; tile_of_index
+// gives tile L of that order.
 constexpr int TILE_GROUP = 8;
 
-__device__ __forceinline__ void tile_of_block(int b, int nt, int &ti, int &tj, int &lin) {
-  const int ntiles = nt * (nt + 1) / 2;
-  const int xcd = b & 7, loc = b >> 3, q = ntiles >> 3, r = ntiles & 7;
-  int L = xcd * q + (xcd < r ? xcd : r) + loc;
-  lin = L;
+__device__ __forceinline__ void tile_of_index(int L, int nt, int &ti, int &tj) {
   const int ng = (nt + TILE_GROUP - 1) / TILE_GROUP;
   for (int gr = 0; gr < ng; ++gr) {
     const int r0 = gr * TILE_GROUP, r1 = min(nt, r0 + TILE_GROUP);
@@ -82,7 +76,22 @@ __device__ __forceinline__ void tile_of_block(int b, int nt, int &ti, int &tj, i
       }
     }
   }
-  ti = tj = 0;   // not reached for b < ntiles
+  ti = tj = 0;   // not reached for L < nt (nt + 1) / 2
+}
+
+// Tile of block b of the first nblk blocks, which cover tiles 0 .. nblk-1 of
+// that order.  Blocks are dispatched round-robin over the 8 XCDs; each XCD
+// gets a contiguous run of the order, so the ~64 tiles resident on one XCD
+// at a time fall in one group and read about 2G row panels, which its L2
+// serves.
+__device__ __forceinline__ void tile_of_block(int b, int nblk, int nt, int &ti, int &tj, int &lin) {
+  const int xcd = b & 7, loc = b >> 3, q = nblk >> 3, r = nblk & 7;
+  lin = xcd * q + (xcd < r ? xcd : r) + loc;
+  tile_of_index(lin, nt, ti, tj);
+}
+
+__device__ __forceinline__ void tile_of_block(int b, int nt, int &ti, int &tj, int &lin) {
+  tile_of_block(b, nt * (nt + 1) / 2, nt, ti, tj, lin);
 }
 
 // LDS geometry of the FP64 / FP32 tile product: K stages of 128 bytes per
@@ -98,18 +107,19 @@ template <int P> struct MmaCfg {
   static constexpr int SMEM = 2 * NP * TILE * LDR; // elements of LDS
 };
 
-// acc[bi][bj] = A[arow0 + wm*64 + bi*16 .. , :] * B[brow0 + wn*64 + bj*16 .., :]^T
-// over the whole K = Mp.  Planes of a multi-plane operand are PS elements
-// apart (FP64 / FP32 storage has one).  FP32 accumulates each run of `fold`
-// K stages in a chunk accumulator and adds it into a running total (fold <=
-// 0: fp32_fold(Mp)); FP64 keeps one accumulator.  Ends with a barrier: smem
-// is free.
+// acc[bi][bj] = A[arow0 + wm*64 + bi*16 .. , K] * B[brow0 + wn*64 + bj*16 .., K]^T
+// over the K stages [kb, ke) of KT values each (ke < 0: the whole K = Mp).
+// Planes of a multi-plane operand are PS elements apart (FP64 / FP32 storage
+// has one).  FP32 accumulates each run of `fold` K stages in a chunk
+// accumulator and adds it into a running total (fold <= 0: fp32_fold(Mp));
+// FP64 keeps one accumulator.  Ends with a barrier: smem is free.
 template <int P>
 __device__ __forceinline__ void mma_tile(const typename Enc<P>::T *__restrict__ Ag,
                                          const typename Enc<P>::T *__restrict__ Bg,
                                          int64_t arow0, int64_t brow0, int64_t Mp, int64_t PS,
                                          typename Enc<P>::T *smem, int fold,
-                                         typename AccType<Enc<P>::KIND>::type (&acc)[4][4]) {
+                                         typename AccType<Enc<P>::KIND>::type (&acc)[4][4],
+                                         int kb = 0, int ke = -1) {
   using C = MmaCfg<P>;
   using T = typename C::T;
   constexpr int NP = C::NP, KT = C::KT, EPC = C::EPC, LDR = C::LDR, CPR = C::CPR, CPT = C::CPT;
@@ -150,12 +160,12 @@ __device__ __forceinline__ void mma_tile(const typename Enc<P>::T *__restrict__ 
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = tot[bi][bj] = Acc{};
 
-  const int nk = (int)(Mp / KT);
+  const int nk = ke < 0 ? (int)(Mp / KT) : ke;
   const int f = fold > 0 ? fold : fp32_fold(Mp);
-  gload(0);
+  gload(kb);
   swrite();
   __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
+  for (int kt = kb; kt < nk; ++kt) {
     if (kt + 1 < nk) gload(kt + 1);
 #pragma unroll
     for (int ks = 0; ks < KT / 4; ++ks) {
@@ -169,7 +179,7 @@ __device__ __forceinline__ void mma_tile(const typename Enc<P>::T *__restrict__ 
         for (int bj = 0; bj < 4; ++bj) acc[bi][bj] = mfma(af, bf[bj], acc[bi][bj]);
       }
     }
-    if (FOLD && ((kt + 1) % f == 0 || kt == nk - 1)) {
+    if (FOLD && ((kt - kb + 1) % f == 0 || kt == nk - 1)) {
 #pragma unroll
       for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
