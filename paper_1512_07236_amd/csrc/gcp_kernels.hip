@@ -118,19 +118,50 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
   double a_coef = 0.0, b_coef = 0.0, e_coef = 0.0;
   if (g.mode == 1) update_coefs(g.method, g.coef[0], a_coef, b_coef, e_coef);
 
+  // The element inputs of BJC column blocks of a row block at a time are
+  // loaded before any of their stores: read per element after the stores
+  // before it, each would wait for them (the compiler cannot tell the output
+  // from the inputs), one memory round trip per element.  (FP64 loads half a
+  // row block: a whole one would spill.)
+  constexpr int BJC = sizeof(T) == 8 ? 1 : 4;
+  double rDj[4];
 #pragma unroll
-  for (int bi = 0; bi < 4; ++bi)
+  for (int bj = 0; bj < 4; ++bj) rDj[bj] = g.rD[brow0 + wn * 64 + bj * 16 + l16];
 #pragma unroll
-    for (int bj = 0; bj < 4; ++bj)
+  for (int bi = 0; bi < 4; ++bi) {
+    double rDi[4], s2i[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = arow0 + wm * 64 + bi * 16 + acc_row<KIND>(lg, r);
+      rDi[r] = g.rD[i];
+      s2i[r] = g.mode == 1 ? g.s2[i] : 0.0;
+    }
+#pragma unroll
+    for (int b0 = 0; b0 < 4; b0 += BJC) {
+    T dpb[BJC][4][NP], xpb[BJC][4][NP];
+#pragma unroll
+    for (int q = 0; q < BJC; ++q)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
+        const int64_t i = arow0 + wm * 64 + bi * 16 + acc_row<KIND>(lg, r);
+        const int64_t j = brow0 + wn * 64 + (b0 + q) * 16 + l16;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          dpb[q][r][p] = Bg[p * PS + i * Mp + j];                        // D(i, j)
+          xpb[q][r][p] = g.mode == 1 ? Ag[p * PS + i * Mp + j] : T{};    // X2(i, j)
+        }
+      }
+#pragma unroll
+    for (int q = 0; q < BJC; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int bj = b0 + q;
         const int64_t i = arow0 + wm * 64 + bi * 16 + acc_row<KIND>(lg, r);
         const int64_t j = brow0 + wn * 64 + bj * 16 + l16;
         if (diag_tile && i > j) continue;   // covered by the mirror of (j, i)
         const double v = (double)acc0[bi][bj][r] * S;
-        T dp[NP], op[NP];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) dp[p] = Bg[p * PS + i * Mp + j];   // D(i, j)
+        const T *dp = dpb[q][r];
+        T op[NP];
         double prod, diff;
         if (g.mode == 0) {
           // X2 = (D_enc + diag(rD))^2: exact diagonal-residual correction
@@ -140,7 +171,7 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
             x2 = g.d2[i];
           } else {
             Dm = E::dec(dp);
-            x2 = v + Dm * (g.rD[i] + g.rD[j]);
+            x2 = v + Dm * (rDi[r] + rDj[bj]);
           }
           E::enc(x2, op);
           const double x2m = (i == j) ? x2 : E::dec(op);
@@ -153,13 +184,10 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
             Dm = g.dg[i];
             dn = a_coef * Dm + b_coef * g.d2[i] + e_coef * g.d3[i];
           } else {
-            T xp[NP];
-#pragma unroll
-            for (int p = 0; p < NP; ++p) xp[p] = Ag[p * PS + i * Mp + j];   // X2(i, j)
             Dm = E::dec(dp);
-            const double X2m = E::dec(xp);
+            const double X2m = E::dec(xpb[q][r]);
             // X3 = (X2_enc + diag(s2)) (D_enc + diag(rD))
-            const double x3 = v + X2m * g.rD[j] + g.s2[i] * Dm;
+            const double x3 = v + X2m * rDj[bj] + s2i[r] * Dm;
             dn = a_coef * Dm + b_coef * X2m + e_coef * x3;
           }
           E::enc(dn, op);
@@ -184,6 +212,8 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
           tacc += diff * diff;
         }
       }
+    }
+  }
 
   // lane reductions (fixed order): rows over the 16 lanes of a column group,
   // columns over the 4 row groups, the tile scalar over the wave
