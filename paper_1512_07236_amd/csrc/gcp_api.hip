@@ -244,9 +244,9 @@ static void PrecCfgInit(gcp_ctx *c, int k) {
   // partial round of np % CUs pairs would leave most CUs idle, so each of
   // those pairs is split along K over up to min(CUs / tail, 4) blocks (at
   // least 8 K stages each) and finished by the last of its splits.  At
-  // M = 8192 (32 tail pairs) 4 splits measured 2.06 ms per product against
-  // 2.24 unsplit and 2.14 with 8 (each split re-pays the pipeline fill and
-  // writes a 128 KB partial).
+  // M = 8192 (32 tail pairs) 2, 4 and 8 splits measured 1.63, 1.63 and
+  // 1.62 ms per product (FP16X3), 3.16, 3.01 and 3.02 ms (BF16X6); each
+  // split re-pays the pipeline fill and writes a 128 KB partial.
   const int tail = npairs % cus;
   int S = tail > 0 ? cus / tail : 1;
   if (S > nk / 8) S = nk / 8;
