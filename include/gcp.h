@@ -198,7 +198,9 @@ int gcp_options_default(gcp_options *opt);
 
 /* Creates a context for M x M problems on the current device and the given
  * stream and allocates its device workspace (four copies of the operand
- * encoding of an M x M matrix plus O(M^2 / 64) FP64 partial sums).  M >= 1;
+ * encoding of an M x M matrix, O(M^2 / 64) FP64 partial sums, and 128 KB per
+ * block of a product whose tiles are split along K: at most 16 MB for
+ * M <= GCP_STATIC_MAX_M and 64 MB above, more with the ksplit option).  M >= 1;
  * M is padded internally to a multiple of 256 with zero rows/columns (exact:
  * the padding is an invariant zero block).  *ctx is set to NULL on failure. */
 int gcp_create(gcp_ctx **ctx, int64_t M, const gcp_options *opt, void *stream);
