@@ -14,8 +14,9 @@ FP64 sum of D_n o D_n.  The initial guess is checked against the oracle's
 D_0 within one encoding rounding.
 
 Sizes: M = 640 and 1000 (padded to 768 and 1024: ragged tails, every tile
-pair split along K, diagonal-tile mirrors) and M = 3900 (padded to 4096:
-256 whole pairs plus a K-split tail of 16 pairs, the launch shapes of the
+pair, and every FP64/FP32 tile, split along K, diagonal-tile mirrors) and
+M = 3900 (padded to 4096: 256 whole pairs plus a K-split tail of 16 pairs;
+512 whole FP64/FP32 tiles plus 16 split 8 ways; the launch shapes of the
 full-size runs).
 """
 import math
@@ -118,10 +119,11 @@ def test_one_update_at_a_time_small(M, N, precision):
         check_step(it[n], it[n + 1], hist[n], precision, label=f"{precision} M={M}")
 
 
-@pytest.mark.parametrize("precision", ["fp16x3", "bf16x6", "fp32"])
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x6", "fp32", "fp64"])
 def test_one_update_at_a_time_whole_pairs_and_tail(precision):
     """M = 3900 (padded 4096): the 16-bit kernel computes 256 whole tile
-    pairs and splits the remaining 16 along K; the FP32 kernel 528 tiles."""
+    pairs and splits the remaining 16 along K; the FP64/FP32 kernel computes
+    512 whole tiles of its 528 and splits the other 16 over 8 blocks each."""
     w = workloads.spectral(3900, 1500, gap=0.1, seed=3900)
     log(f"[gpu] element-wise {precision} M=3900")
     steps = [0, 1]
