@@ -26,6 +26,11 @@ __device__ __forceinline__ double bf2d(uint16_t h) {
   return (double)__uint_as_float((uint32_t)h << 16);
 }
 __device__ __forceinline__ uint16_t f2h(float f) {
+  // float -> float16, round to nearest even.  The empty asm keeps f a float
+  // in a register: without it the compiler folds a preceding double -> float
+  // conversion into one double -> float16 conversion, which has no
+  // instruction and is emulated in about 35 integer operations per element.
+  asm volatile("" : "+v"(f));
   _Float16 h = (_Float16)f;
   return __builtin_bit_cast(uint16_t, h);
 }
