@@ -523,8 +523,14 @@ def main() -> int:
         "host_syncs": r0.host_syncs,
         "iterations_per_s": p / t_mixed,
         "termination_product": {"launches": launches - 2 * p,
-                                "note": "the stop on Tr(D Dbar) is decided from the last "
-                                        "update's traces; no product is launched for it",
+                                "note": ("the stop on Tr(D Dbar) was decided from the last "
+                                         "update's traces; no product was launched for it")
+                                if launches == 2 * p else
+                                ("the last update's Tr(D Dbar) was above the tolerance, so "
+                                 "one more D^2 was formed to decide the stop (at the "
+                                 "encoding's rounding floor: status STOPPED_AT_FLOOR)")
+                                if r0.status == gcp.STOPPED_AT_FLOOR else
+                                "one more D^2 was formed to decide the stop",
                                 "tflops_incl": launches * flops_product / t_mixed / 1e12},
         "err": err_m,
         "trace_err": tr_m,
