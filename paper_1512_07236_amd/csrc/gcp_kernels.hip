@@ -1060,8 +1060,12 @@ __global__ __launch_bounds__(256) void k_reduce(RedArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   double w = 0.0;
-  if (i < a.Mp)
+  if (i < a.Mp) {
+    // unrolled so that the loads are in flight together; the adds keep
+    // their order
+#pragma unroll 8
     for (int s = q; s < a.nslots; s += 4) w += a.part[(int64_t)s * a.Mp + i];
+  }
   rq[q][lane] = w;
   __syncthreads();
   double v = 0.0, e = 0.0;
