@@ -158,53 +158,53 @@ __global__ __launch_bounds__(NTH, 2) void k_bgemm(BwdArgs a) {
 #pragma unroll
     for (int b0 = 0; b0 < 4; b0 += BJC)
 #pragma unroll
-    for (int r0 = 0; r0 < 4; r0 += RC) {
-      T in[BJC][RC][NIN];
+      for (int r0 = 0; r0 < 4; r0 += RC) {
+        T in[BJC][RC][NIN];
 #pragma unroll
-      for (int q = 0; q < BJC; ++q)
+        for (int q = 0; q < BJC; ++q)
 #pragma unroll
-        for (int rr = 0; rr < RC; ++rr) {
-          const int r = r0 + rr;
-          const int64_t i = arow0 + wm * 64 + bi * 16 + acc_row<KIND>(lg, r);
-          const int64_t j = brow0 + wn * 64 + (b0 + q) * 16 + l16;
-          in[q][rr][0] = D[i * Mp + j];
-          in[q][rr][1] = G[i * Mp + j];
-          if constexpr (MODE == 2) {
-            in[q][rr][2] = X2[i * Mp + j];
-            in[q][rr][3] = AT[i * Mp + j];
-            in[q][rr][4] = AT[j * Mp + i];
-            in[q][rr][5] = CT[i * Mp + j];
-            in[q][rr][6] = CT[j * Mp + i];
+          for (int rr = 0; rr < RC; ++rr) {
+            const int r = r0 + rr;
+            const int64_t i = arow0 + wm * 64 + bi * 16 + acc_row<KIND>(lg, r);
+            const int64_t j = brow0 + wn * 64 + (b0 + q) * 16 + l16;
+            in[q][rr][0] = D[i * Mp + j];
+            in[q][rr][1] = G[i * Mp + j];
+            if constexpr (MODE == 2) {
+              in[q][rr][2] = X2[i * Mp + j];
+              in[q][rr][3] = AT[i * Mp + j];
+              in[q][rr][4] = AT[j * Mp + i];
+              in[q][rr][5] = CT[i * Mp + j];
+              in[q][rr][6] = CT[j * Mp + i];
+            }
           }
-        }
 #pragma unroll
-      for (int q = 0; q < BJC; ++q)
+        for (int q = 0; q < BJC; ++q)
 #pragma unroll
-        for (int rr = 0; rr < RC; ++rr) {
-          const int bj = b0 + q, r = r0 + rr;
-          const int64_t i = arow0 + wm * 64 + bi * 16 + acc_row<KIND>(lg, r);
-          const int64_t j = brow0 + wn * 64 + bj * 16 + l16;
-          if (diag_tile && i > j) continue;   // covered by the mirror of (j, i)
-          const double v = (double)acc[bi][bj][r];
-          const double d = (double)in[q][rr][0];
-          double o;
-          if constexpr (MODE == 0) {
-            o = v;
-            const double wg = ((i == j) ? 1.0 : 2.0) * (double)in[q][rr][1];
-            tsum += wg * (double)(T)v;
-            dsum += wg * d;
-          } else {
-            const double g = (double)in[q][rr][1];
-            const double x2 = (double)in[q][rr][2];
-            const double at = (double)in[q][rr][3] + (double)in[q][rr][4];
-            const double ct = (double)in[q][rr][5] + (double)in[q][rr][6];
-            const double gc = ((2.0 * d - 3.0 * x2) - a.c * ((i == j ? 1.0 : 0.0) - 2.0 * d)) * a.inv_t12;
-            o = a.a * g + a.b * at + a.e * (ct + v) + kappa * gc;
+          for (int rr = 0; rr < RC; ++rr) {
+            const int bj = b0 + q, r = r0 + rr;
+            const int64_t i = arow0 + wm * 64 + bi * 16 + acc_row<KIND>(lg, r);
+            const int64_t j = brow0 + wn * 64 + bj * 16 + l16;
+            if (diag_tile && i > j) continue;   // covered by the mirror of (j, i)
+            const double v = (double)acc[bi][bj][r];
+            const double d = (double)in[q][rr][0];
+            double o;
+            if constexpr (MODE == 0) {
+              o = v;
+              const double wg = ((i == j) ? 1.0 : 2.0) * (double)in[q][rr][1];
+              tsum += wg * (double)(T)v;
+              dsum += wg * d;
+            } else {
+              const double g = (double)in[q][rr][1];
+              const double x2 = (double)in[q][rr][2];
+              const double at = (double)in[q][rr][3] + (double)in[q][rr][4];
+              const double ct = (double)in[q][rr][5] + (double)in[q][rr][6];
+              const double gc = ((2.0 * d - 3.0 * x2) - a.c * ((i == j ? 1.0 : 0.0) - 2.0 * d)) * a.inv_t12;
+              o = a.a * g + a.b * at + a.e * (ct + v) + kappa * gc;
+            }
+            O[i * Mp + j] = (T)o;
+            if (i != j) O[j * Mp + i] = (T)o;
           }
-          O[i * Mp + j] = (T)o;
-          if (i != j) O[j * Mp + i] = (T)o;
-        }
-    }
+      }
 
   if constexpr (MODE == 0) {
 #pragma unroll

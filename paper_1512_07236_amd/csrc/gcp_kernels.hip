@@ -138,80 +138,80 @@ __global__ __launch_bounds__(NTH, 2) void k_gemm(GemmArgs g) {
     }
 #pragma unroll
     for (int b0 = 0; b0 < 4; b0 += BJC) {
-    T dpb[BJC][4][NP], xpb[BJC][4][NP];
+      T dpb[BJC][4][NP], xpb[BJC][4][NP];
 #pragma unroll
-    for (int q = 0; q < BJC; ++q)
+      for (int q = 0; q < BJC; ++q)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t i = arow0 + wm * 64 + bi * 16 + acc_row<KIND>(lg, r);
-        const int64_t j = brow0 + wn * 64 + (b0 + q) * 16 + l16;
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = arow0 + wm * 64 + bi * 16 + acc_row<KIND>(lg, r);
+          const int64_t j = brow0 + wn * 64 + (b0 + q) * 16 + l16;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          dpb[q][r][p] = Bg[p * PS + i * Mp + j];                        // D(i, j)
-          xpb[q][r][p] = g.mode == 1 ? Ag[p * PS + i * Mp + j] : T{};    // X2(i, j)
+          for (int p = 0; p < NP; ++p) {
+            dpb[q][r][p] = Bg[p * PS + i * Mp + j];                        // D(i, j)
+            xpb[q][r][p] = g.mode == 1 ? Ag[p * PS + i * Mp + j] : T{};    // X2(i, j)
+          }
         }
-      }
 #pragma unroll
-    for (int q = 0; q < BJC; ++q)
+      for (int q = 0; q < BJC; ++q)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int bj = b0 + q;
-        const int64_t i = arow0 + wm * 64 + bi * 16 + acc_row<KIND>(lg, r);
-        const int64_t j = brow0 + wn * 64 + bj * 16 + l16;
-        if (diag_tile && i > j) continue;   // covered by the mirror of (j, i)
-        const double v = (double)acc0[bi][bj][r] * S;
-        const T *dp = dpb[q][r];
-        T op[NP];
-        double prod, diff;
-        if (g.mode == 0) {
-          // X2 = (D_enc + diag(rD))^2: exact diagonal-residual correction
-          double Dm, x2;
-          if (i == j) {
-            Dm = g.dg[i];
-            x2 = g.d2[i];
+        for (int r = 0; r < 4; ++r) {
+          const int bj = b0 + q;
+          const int64_t i = arow0 + wm * 64 + bi * 16 + acc_row<KIND>(lg, r);
+          const int64_t j = brow0 + wn * 64 + bj * 16 + l16;
+          if (diag_tile && i > j) continue;   // covered by the mirror of (j, i)
+          const double v = (double)acc0[bi][bj][r] * S;
+          const T *dp = dpb[q][r];
+          T op[NP];
+          double prod, diff;
+          if (g.mode == 0) {
+            // X2 = (D_enc + diag(rD))^2: exact diagonal-residual correction
+            double Dm, x2;
+            if (i == j) {
+              Dm = g.dg[i];
+              x2 = g.d2[i];
+            } else {
+              Dm = E::dec(dp);
+              x2 = v + Dm * (rDi[r] + rDj[bj]);
+            }
+            E::enc(x2, op);
+            const double x2m = (i == j) ? x2 : E::dec(op);
+            if (i == j) g.s2[i] = x2 - E::dec(op);
+            prod = x2m * Dm;
+            diff = x2m - Dm;
           } else {
-            Dm = E::dec(dp);
-            x2 = v + Dm * (rDi[r] + rDj[bj]);
+            double Dm, dn;
+            if (i == j) {
+              Dm = g.dg[i];
+              dn = a_coef * Dm + b_coef * g.d2[i] + e_coef * g.d3[i];
+            } else {
+              Dm = E::dec(dp);
+              const double X2m = E::dec(xpb[q][r]);
+              // X3 = (X2_enc + diag(s2)) (D_enc + diag(rD))
+              const double x3 = v + X2m * rDj[bj] + s2i[r] * Dm;
+              dn = a_coef * Dm + b_coef * X2m + e_coef * x3;
+            }
+            E::enc(dn, op);
+            const double dnm = (i == j) ? dn : E::dec(op);
+            if (i == j) {
+              g.dg_new[i] = dn;
+              g.rD_new[i] = dn - E::dec(op);
+            }
+            prod = dnm * dnm;
+            diff = dnm - Dm;
           }
-          E::enc(x2, op);
-          const double x2m = (i == j) ? x2 : E::dec(op);
-          if (i == j) g.s2[i] = x2 - E::dec(op);
-          prod = x2m * Dm;
-          diff = x2m - Dm;
-        } else {
-          double Dm, dn;
-          if (i == j) {
-            Dm = g.dg[i];
-            dn = a_coef * Dm + b_coef * g.d2[i] + e_coef * g.d3[i];
-          } else {
-            Dm = E::dec(dp);
-            const double X2m = E::dec(xpb[q][r]);
-            // X3 = (X2_enc + diag(s2)) (D_enc + diag(rD))
-            const double x3 = v + X2m * rDj[bj] + s2i[r] * Dm;
-            dn = a_coef * Dm + b_coef * X2m + e_coef * x3;
-          }
-          E::enc(dn, op);
-          const double dnm = (i == j) ? dn : E::dec(op);
-          if (i == j) {
-            g.dg_new[i] = dn;
-            g.rD_new[i] = dn - E::dec(op);
-          }
-          prod = dnm * dnm;
-          diff = dnm - Dm;
-        }
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          Og[p * PS + i * Mp + j] = op[p];
-          if (i != j) Og[p * PS + j * Mp + i] = op[p];
+          for (int p = 0; p < NP; ++p) {
+            Og[p * PS + i * Mp + j] = op[p];
+            if (i != j) Og[p * PS + j * Mp + i] = op[p];
+          }
+          rowacc[bi][r] += prod;
+          if (i != j) {
+            colacc[bj] += prod;
+            tacc += 2.0 * diff * diff;
+          } else {
+            tacc += diff * diff;
+          }
         }
-        rowacc[bi][r] += prod;
-        if (i != j) {
-          colacc[bj] += prod;
-          tacc += 2.0 * diff * diff;
-        } else {
-          tacc += diff * diff;
-        }
-      }
     }
   }
 
